@@ -1,0 +1,180 @@
+/*
+ * zd.h -- C ABI of libzd, an MI355X (gfx950) implementation of the zd-tree
+ * for exact k-nearest neighbours in 2 and 3 dimensions.
+ *
+ * Method: G. E. Blelloch and M. Dobson, "Parallel Nearest Neighbors in Low
+ * Dimensions with Batch Updates" (arXiv 2111.04182).  The tree is a kd-tree
+ * whose splits follow the bits of the Morton order of the randomly shifted,
+ * integer-rounded points (Section 2, "Data structure" and "Construction");
+ * k-NN searches climb from a leaf and descend into sibling subtrees with box
+ * pruning (Algorithms 2 and 3); batches of points are inserted and deleted
+ * (Algorithm 4 and Section 2, "Batch-dynamic updates").
+ *
+ * Conventions shared by every call:
+ *   - Pointers marked (device) are HIP device pointers; (host) are host
+ *     pointers.  Coordinates are structure-of-arrays FP64 in one buffer:
+ *     x[0..n), y[0..n), then z[0..n) in 3D.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *     Calls are stream-ordered: inputs may be reused once the stream has
+ *     passed the call.
+ *   - The caller owns every input and output buffer.  The library keeps its
+ *     own copies of what it needs (the Morton-ordered points, the nodes, the
+ *     id map) and frees them in zd_free.
+ *   - Errors are returned before anything is enqueued; out-parameters are
+ *     untouched on error.  No C++ exception crosses this interface.
+ *   - Squared distances d2(a,b) = ((dx*dx + dy*dy) + dz*dz), dx = a.x - b.x,
+ *     binary64 with no fused multiply-add.  Neighbours are ordered by
+ *     (d2, id) ascending; equal d2 goes to the lower id.  Results are exact:
+ *     they equal brute force over the live points bit for bit.
+ */
+#ifndef ZD_H
+#define ZD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ZD_API __attribute__((visibility("default")))
+
+typedef struct zd_tree_s *zd_tree;
+typedef struct zd_forest_s *zd_forest;
+
+typedef enum {
+  ZD_OK = 0,
+  ZD_EINVAL = 1,  /* invalid argument */
+  ZD_EBOUNDS = 2, /* an inserted point lies outside the declared box */
+  ZD_EID = 3,     /* a deleted id is out of range, dead, or repeated */
+  ZD_ENOMEM = 4,  /* device allocation failed */
+  ZD_EDEVICE = 5, /* a HIP call failed; only zd_free remains valid */
+  ZD_EKMAX = 6    /* k exceeds ZD_KMAX */
+} zd_status;
+
+/* largest supported k */
+#define ZD_KMAX 64
+
+/* Build parameters.
+ *   dim:        2 or 3.
+ *   leaf_size:  L >= 1, the most points a leaf holds (a leaf whose points all
+ *               share one Morton key may hold more: Algorithm 1's "no bits
+ *               left" case).  The paper calls L + 1 its sizeCutoff.
+ *   shift_seed: seed of the random shift (Section 2, "Construction"): shift
+ *               c = splitmix64 output number c+1 from the seed, reduced mod
+ *               2^(B-1), B = 64/dim bits per coordinate.  Results do not
+ *               depend on it, only the tree shape does.
+ *   shift:      (host) [dim] explicit shift values in [0, 2^(B-1)), or NULL
+ *               to draw them from shift_seed.
+ *   box_lo/hi:  (host) [dim] the box that every point, including later
+ *               inserts, must lie in (Section 2: the box is declared before
+ *               the first build), or both NULL to use the bounding cube of
+ *               the build points (lo = per-coordinate minimum, common side =
+ *               the largest extent, 1 if all points coincide).  Rounding to
+ *               integers (Section 3.1) maps [lo, hi] onto 2^(B-1) cells per
+ *               coordinate: cell = clamp(floor((x - lo) * S), 0, 2^(B-1)-1),
+ *               S = 2^(B-1) / (hi - lo). */
+typedef struct {
+  int32_t dim;
+  int32_t leaf_size;
+  uint64_t shift_seed;
+  const uint64_t *shift;
+  const double *box_lo;
+  const double *box_hi;
+} zd_params;
+
+/* Build a zd-tree over n points (Section 2, "Construction", Algorithm 1).
+ *   xyz: (device) SoA [dim][n] FP64 coordinates.  Point i gets id i.
+ *   out: (host) receives the new tree handle.
+ * Asynchronous on `stream` when a box is given; with box_lo == NULL the call
+ * synchronises `stream` once to read the data's bounding cube.
+ * Errors: ZD_EINVAL for a NULL params/out, dim not 2 or 3, leaf_size < 1,
+ * n < 0, n > 2^31 - 2, a NULL xyz with n > 0, n == 0 without a box, only one
+ * of box_lo / box_hi given, hi <= lo, a non-finite box, or a shift value out
+ * of range; ZD_ENOMEM; ZD_EDEVICE. */
+ZD_API zd_status zd_build(const zd_params *params, const double *xyz, int64_t n,
+                   void *stream, zd_tree *out);
+
+/* Exact k-NN queries (Algorithms 2 and 3).
+ *   q_xyz == NULL: the k-nearest-neighbour graph of the live points
+ *     (Section 1.1; the paper's leaf-based search, Section 2): one row per
+ *     id in [0, id_capacity); row p holds the k nearest live points q != p.
+ *     m must equal the id capacity (zd_info).  Rows of deleted ids are
+ *     filled with (-1, +inf).
+ *   q_xyz != NULL: (device) SoA [dim][m] dynamic query points (Section 1.1;
+ *     the bit-based search of Section 2: descend by the query's Morton bits,
+ *     then climb).  Row r answers query r; nothing is excluded.  Queries
+ *     outside the box are allowed (their integer coordinates are clamped).
+ *   out_ids: (device) [m][k] int32 neighbour ids, out_d2: (device) [m][k]
+ *     FP64 squared distances; each row ascending by (d2, id); a row with
+ *     fewer than k candidates is padded with (-1, +inf).
+ * Asynchronous.  Concurrent zd_knn calls on one tree are safe.
+ * Errors: ZD_EINVAL (NULL tree or outputs, m < 0, k < 1, m mismatch),
+ * ZD_EKMAX (k > ZD_KMAX), ZD_ENOMEM, ZD_EDEVICE. */
+ZD_API zd_status zd_knn(zd_tree tree, const double *q_xyz, int64_t m, int32_t k,
+                 int32_t *out_ids, double *out_d2, void *stream);
+
+/* Batch insertion (Algorithm 4).  The m new points get ids id_capacity,
+ * id_capacity + 1, ...; the id capacity grows by m.
+ *   xyz: (device) SoA [dim][m].  out_new_ids: (device) [m] or NULL.
+ * The batch is all-or-nothing: if any point lies outside the declared box
+ * the call returns ZD_EBOUNDS and the tree is unchanged.  Afterwards the tree
+ * equals a fresh build of the live points (same box and shift).
+ * Synchronises `stream` (to validate the batch).
+ * Errors: ZD_EINVAL, ZD_EBOUNDS, ZD_ENOMEM, ZD_EDEVICE. */
+ZD_API zd_status zd_insert_batch(zd_tree tree, const double *xyz, int64_t m,
+                          int32_t *out_new_ids, void *stream);
+
+/* Batch deletion (Section 2, "Batch-dynamic updates").
+ *   ids: (device) [m] int32 ids to delete.
+ * All-or-nothing: an id out of range, already deleted, or repeated in the
+ * batch gives ZD_EID with the tree unchanged.  Afterwards the tree equals a
+ * fresh build of the live points.  Synchronises `stream`.
+ * Errors: ZD_EINVAL, ZD_EID, ZD_ENOMEM, ZD_EDEVICE. */
+ZD_API zd_status zd_delete_batch(zd_tree tree, const int32_t *ids, int64_t m,
+                          void *stream);
+
+/* Release a tree.  The release is ordered on the stream of the tree's last
+ * call; the caller must not have work using the tree on other streams.
+ * zd_free(NULL) is a no-op. */
+ZD_API zd_status zd_free(zd_tree tree);
+
+/* Sizes of a tree: live points, id capacity (rows of an all-points query),
+ * leaves, internal nodes.  Any pointer may be NULL.  Synchronises the tree's
+ * stream. */
+ZD_API zd_status zd_info(zd_tree tree, int64_t *n_live, int64_t *id_capacity,
+                  int64_t *n_leaves, int64_t *n_internal);
+
+/* Copy the tree to caller-owned host arrays in its canonical in-order form
+ * (for tests): the live (key, id) pairs in Morton order, every leaf's size
+ * and tight box, and every internal node's split bit and tight box, in
+ * order (leaf 0, internal 0, leaf 1, ..., leaf n_leaves-1).  Sizes come from
+ * zd_info; boxes are [count][dim].  The box lo/scale/shift used for the keys
+ * go to params_out = {lo[dim], hi[dim], S[dim]} and shift_out[dim].  Any
+ * pointer may be NULL.  Synchronises the tree's stream. */
+ZD_API zd_status zd_export(zd_tree tree, uint64_t *keys, int32_t *ids,
+                    int64_t *leaf_count, double *leaf_lo, double *leaf_hi,
+                    int32_t *int_bit, double *int_lo, double *int_hi,
+                    double *params_out, uint64_t *shift_out);
+
+/* Backward of the k-NN squared distances for a fixed neighbour table.
+ * For L = sum over rows r and slots j of grad_d2[r][j] * d2(p_r, p_q),
+ * q = ids[r][j] (entries with q < 0 are skipped):
+ *   dL/dp_r += 2 (p_r - p_q) g,   dL/dp_q -= 2 (p_r - p_q) g.
+ *   xyz:  (device) SoA [dim][stride] points by id (row r is id r).
+ *   ids, grad_d2: (device) [rows][k].   grad_xyz: (device) SoA [dim][stride],
+ *   overwritten.  Accumulation uses FP64 atomics, so the summation order
+ *   (not the set of terms) varies between runs.
+ * Asynchronous.  Errors: ZD_EINVAL, ZD_EDEVICE. */
+ZD_API zd_status zd_knn_backward(int32_t dim, const double *xyz, int64_t stride,
+                          int64_t rows, int32_t k, const int32_t *ids,
+                          const double *grad_d2, double *grad_xyz,
+                          void *stream);
+
+/* A short English description of a status code (static storage). */
+ZD_API const char *zd_status_str(zd_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZD_H */

@@ -1,0 +1,13 @@
+"""zd-tree exact k-nearest neighbours on MI355X (gfx950).
+
+The compute path is libzd.so (hand-written HIP kernels behind the C ABI in
+include/zd.h); this package is its thin binding.  PyTorch provides device
+memory and streams only.
+"""
+from ._lib import (ZD_KMAX, ZdError, ZdTree, lib, soa, zd_build, zd_delete_batch, zd_export,
+                   zd_free, zd_info, zd_insert_batch, zd_knn, zd_knn_backward)
+from .autograd import ZdKnnSqDist, knn_sq_dist
+
+__all__ = ["ZD_KMAX", "ZdError", "ZdTree", "ZdKnnSqDist", "knn_sq_dist", "lib", "soa",
+           "zd_build", "zd_delete_batch", "zd_export", "zd_free", "zd_info",
+           "zd_insert_batch", "zd_knn", "zd_knn_backward"]

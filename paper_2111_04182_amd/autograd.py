@@ -1,0 +1,38 @@
+"""Differentiable k-NN squared distances.
+
+``ZdKnnSqDist.apply(xyz, tree, k)`` returns (d2, ids) for the all-points
+k-NN rows of ``tree``; d2 is differentiable with respect to the SoA point
+tensor ``xyz`` (d, cap), which must hold the tree's points by id.  The
+neighbour set is chosen exactly and held fixed: the backward pass is the
+library's scatter-add kernel (zd_knn_backward),
+    dL/dp += 2 (p - q) g,   dL/dq -= 2 (p - q) g,
+for every row p, neighbour q and upstream gradient g.  Selection itself is
+not differentiated, as usual for nearest-neighbour losses.
+"""
+from __future__ import annotations
+
+import torch
+
+from ._lib import ZdTree, zd_knn_backward
+
+
+class ZdKnnSqDist(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, xyz: torch.Tensor, tree: ZdTree, k: int):
+        ids, d2 = tree.knn(k)
+        ctx.save_for_backward(xyz, ids)
+        ctx.mark_non_differentiable(ids)
+        return d2, ids
+
+    @staticmethod
+    def backward(ctx, grad_d2, grad_ids):
+        xyz, ids = ctx.saved_tensors
+        g = torch.zeros(ids.shape, dtype=torch.float64, device=xyz.device) if grad_d2 is None \
+            else grad_d2.contiguous()
+        grad = zd_knn_backward(xyz.detach(), ids, g)
+        return grad, None, None
+
+
+def knn_sq_dist(xyz: torch.Tensor, tree: ZdTree, k: int):
+    """Functional form of ZdKnnSqDist."""
+    return ZdKnnSqDist.apply(xyz, tree, k)

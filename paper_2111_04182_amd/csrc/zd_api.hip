@@ -1,0 +1,543 @@
+// zd_api.hip -- the C ABI of libzd (see include/zd.h): argument checks, tree
+// storage, and the order of the device passes behind each call.
+#include "zd_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace zd;
+
+namespace {
+
+// Point-side storage of one tree generation, all sized for n points.  An
+// update builds the next generation from the current one and then releases
+// the current one (stream-ordered), so no array ever needs slack.
+struct Store {
+  int64_t n = 0;
+  uint64_t *key = nullptr;
+  int32_t *id = nullptr;
+  double *X = nullptr, *Y = nullptr, *Z = nullptr;
+  int32_t *leaf_of = nullptr;
+  int32_t *leaf_begin = nullptr;
+  int32_t *leaf_parent = nullptr;
+  INode *inode = nullptr;
+};
+
+hipError_t store_alloc(Store &s, int64_t n, int dim, hipStream_t st) {
+  s.n = n;
+  hipError_t e = dev_alloc_n(&s.key, n, st);
+  if (e == hipSuccess) e = dev_alloc_n(&s.id, n, st);
+  if (e == hipSuccess) e = dev_alloc_n(&s.X, n, st);
+  if (e == hipSuccess) e = dev_alloc_n(&s.Y, n, st);
+  if (e == hipSuccess) e = dim == 3 ? dev_alloc_n(&s.Z, n, st) : hipSuccess;
+  if (e == hipSuccess) e = dev_alloc_n(&s.leaf_of, n, st);
+  if (e == hipSuccess) e = dev_alloc_n(&s.leaf_begin, n + 1, st);
+  if (e == hipSuccess) e = dev_alloc_n(&s.leaf_parent, n, st);
+  if (e == hipSuccess) e = dev_alloc_n(&s.inode, n, st);
+  return e;
+}
+
+void store_release(Store &s, hipStream_t st) {
+  dev_release(s.key, st);
+  dev_release(s.id, st);
+  dev_release(s.X, st);
+  dev_release(s.Y, st);
+  dev_release(s.Z, st);
+  dev_release(s.leaf_of, st);
+  dev_release(s.leaf_begin, st);
+  dev_release(s.leaf_parent, st);
+  dev_release(s.inode, st);
+  s = Store{};
+}
+
+uint64_t splitmix64(uint64_t seed, uint64_t i) {
+  // the published SplitMix64 mixer (Steele, Lea, Flood 2014) at seed + i*gamma
+  uint64_t z = seed + i * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+zd_status to_status(hipError_t e) {
+  if (e == hipSuccess) return ZD_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return ZD_ENOMEM;
+  return ZD_EDEVICE;
+}
+
+}  // namespace
+
+struct zd_tree_s {
+  int dim = 0, L = 0;
+  Geometry geo{};
+  double hi[3] = {0, 0, 0};
+  int64_t cap = 0;   // id capacity
+  int64_t icap = 0;  // allocated length of the id arrays
+  hipStream_t stream = nullptr;
+  bool broken = false;
+  Store st;
+  int32_t *slot_of = nullptr;  // [icap] id -> sorted position, -1 if dead
+  int32_t *mark = nullptr;     // [icap] zero between calls
+  int32_t *meta = nullptr;     // [kMetaCount]
+  double *root_box = nullptr;  // [6]
+
+  TreeView view() const {
+    TreeView v;
+    v.key = st.key;
+    v.id = st.id;
+    v.X = st.X;
+    v.Y = st.Y;
+    v.Z = st.Z;
+    v.leaf_of = st.leaf_of;
+    v.leaf_begin = st.leaf_begin;
+    v.leaf_parent = st.leaf_parent;
+    v.inode = st.inode;
+    v.meta = meta;
+    v.n = st.n;
+    return v;
+  }
+
+  BuildBuffers buffers(int32_t *flag) const {
+    BuildBuffers b;
+    b.key = st.key;
+    b.id = st.id;
+    b.X = st.X;
+    b.Y = st.Y;
+    b.Z = st.Z;
+    b.leaf_of = st.leaf_of;
+    b.leaf_begin = st.leaf_begin;
+    b.leaf_parent = st.leaf_parent;
+    b.inode = st.inode;
+    b.meta = meta;
+    b.root_box = root_box;
+    b.flag = flag;
+    return b;
+  }
+};
+
+namespace {
+
+// Order all later work of the tree after what was enqueued on its previous
+// stream, then make `s` the tree's stream.
+hipError_t bind_stream(zd_tree t, hipStream_t s) {
+  if (s == t->stream) return hipSuccess;
+  hipEvent_t ev;
+  hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(ev, t->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
+  (void)hipEventDestroy(ev);
+  if (e == hipSuccess) t->stream = s;
+  return e;
+}
+
+// Relink the tree over the points of t->st (keys sorted, coordinates and
+// slot map in place).
+hipError_t relink(zd_tree t) {
+  hipStream_t s = t->stream;
+  int32_t *flag = nullptr;
+  hipError_t e = dev_alloc_n(&flag, t->st.n, s);
+  if (e != hipSuccess) return e;
+  e = build_tree_links(t->dim, t->L, t->st.n, t->buffers(flag), s);
+  dev_release(flag, s);
+  return e;
+}
+
+// Grow the id arrays to hold `need` ids (old entries kept, new slots dead).
+hipError_t grow_ids(zd_tree t, int64_t need) {
+  if (need <= t->icap) return hipSuccess;
+  hipStream_t s = t->stream;
+  int64_t ncap = t->icap > 0 ? t->icap : 1024;
+  while (ncap < need) ncap += ncap / 2 + 1;
+  int32_t *slot = nullptr, *mark = nullptr;
+  hipError_t e = dev_alloc_n(&slot, ncap, s);
+  if (e == hipSuccess) e = dev_alloc_n(&mark, ncap, s);
+  if (e == hipSuccess) e = fill_i32(slot, -1, ncap, s);
+  if (e == hipSuccess) e = fill_i32(mark, 0, ncap, s);
+  if (e == hipSuccess && t->cap > 0)
+    e = hipMemcpyAsync(slot, t->slot_of, sizeof(int32_t) * (size_t)t->cap,
+                       hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) {
+    dev_release(slot, s);
+    dev_release(mark, s);
+    return e;
+  }
+  dev_release(t->slot_of, s);
+  dev_release(t->mark, s);
+  t->slot_of = slot;
+  t->mark = mark;
+  t->icap = ncap;
+  return hipSuccess;
+}
+
+bool finite3(const double *v, int dim) {
+  for (int c = 0; c < dim; ++c)
+    if (!std::isfinite(v[c])) return false;
+  return true;
+}
+
+void destroy(zd_tree t) {
+  if (!t) return;
+  hipStream_t s = t->stream;
+  store_release(t->st, s);
+  dev_release(t->slot_of, s);
+  dev_release(t->mark, s);
+  dev_release(t->meta, s);
+  dev_release(t->root_box, s);
+  delete t;
+}
+
+constexpr int64_t kMaxPoints = (int64_t)INT32_MAX - 1;
+
+}  // namespace
+
+extern "C" {
+
+const char *zd_status_str(zd_status status) {
+  switch (status) {
+    case ZD_OK: return "ok";
+    case ZD_EINVAL: return "invalid argument";
+    case ZD_EBOUNDS: return "point outside the declared box";
+    case ZD_EID: return "id out of range, deleted, or repeated";
+    case ZD_ENOMEM: return "device allocation failed";
+    case ZD_EDEVICE: return "device error";
+    case ZD_EKMAX: return "k exceeds ZD_KMAX";
+  }
+  return "unknown status";
+}
+
+zd_status zd_build(const zd_params *p, const double *xyz, int64_t n, void *stream,
+                   zd_tree *out) {
+  if (!p || !out) return ZD_EINVAL;
+  const int dim = p->dim;
+  if ((dim != 2 && dim != 3) || p->leaf_size < 1 || n < 0 || n > kMaxPoints) return ZD_EINVAL;
+  if (n > 0 && !xyz) return ZD_EINVAL;
+  if ((p->box_lo == nullptr) != (p->box_hi == nullptr)) return ZD_EINVAL;
+  if (n == 0 && !p->box_lo) return ZD_EINVAL;
+  const int B = 64 / dim;
+  if (p->box_lo) {
+    if (!finite3(p->box_lo, dim) || !finite3(p->box_hi, dim)) return ZD_EINVAL;
+    for (int c = 0; c < dim; ++c)
+      if (!(p->box_hi[c] > p->box_lo[c])) return ZD_EINVAL;
+  }
+  if (p->shift)
+    for (int c = 0; c < dim; ++c)
+      if (p->shift[c] >> (B - 1)) return ZD_EINVAL;
+
+  zd_tree t = new (std::nothrow) zd_tree_s();
+  if (!t) return ZD_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  t->stream = s;
+  t->dim = dim;
+  t->L = p->leaf_size;
+  t->geo.dim = dim;
+  t->geo.B = B;
+  for (int c = 0; c < dim; ++c)
+    t->geo.shift[c] = p->shift ? p->shift[c]
+                               : (splitmix64(p->shift_seed, (uint64_t)c + 1) &
+                                  ((uint64_t(1) << (B - 1)) - 1));
+
+  hipError_t e = dev_alloc_n(&t->meta, kMetaCount, s);
+  if (e == hipSuccess) e = dev_alloc_n(&t->root_box, 6, s);
+  if (e == hipSuccess) e = fill_i32(t->meta, 0, kMetaCount, s);
+  if (e == hipSuccess) e = fill_f64(t->root_box, 0.0, 6, s);
+  if (e == hipSuccess) {
+    if (p->box_lo) {
+      for (int c = 0; c < dim; ++c) {
+        t->geo.lo[c] = p->box_lo[c];
+        t->hi[c] = p->box_hi[c];
+        t->geo.S[c] = std::ldexp(1.0, B - 1) / (t->hi[c] - t->geo.lo[c]);
+      }
+    } else {
+      // the bounding cube of the data: one read-back
+      double *d = nullptr;
+      double h[6];
+      e = dev_alloc_n(&d, 6, s);
+      if (e == hipSuccess) e = box_reduce(dim, xyz, n, d, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      dev_release(d, s);
+      if (e == hipSuccess) {
+        double side = 0.0;
+        for (int c = 0; c < dim; ++c)
+          if (h[3 + c] - h[c] > side) side = h[3 + c] - h[c];
+        if (!(side > 0.0)) side = 1.0;
+        for (int c = 0; c < dim; ++c) {
+          t->geo.lo[c] = h[c];
+          t->hi[c] = h[c] + side;
+          t->geo.S[c] = std::ldexp(1.0, B - 1) / side;
+        }
+        if (!finite3(t->geo.lo, dim) || !std::isfinite(side)) {
+          destroy(t);
+          return ZD_EINVAL;
+        }
+      }
+    }
+  }
+  if (e == hipSuccess) e = grow_ids(t, n);
+  if (e == hipSuccess) e = store_alloc(t->st, n, dim, s);
+  uint64_t *ktmp = nullptr;
+  int32_t *itmp = nullptr;
+  if (e == hipSuccess && n > 1) e = dev_alloc_n(&ktmp, n, s);
+  if (e == hipSuccess && n > 1) e = dev_alloc_n(&itmp, n, s);
+  if (e == hipSuccess) e = encode_keys(t->geo, xyz, n, n, 0, t->st.key, t->st.id, s);
+  if (e == hipSuccess) e = radix_sort_pairs(t->st.key, t->st.id, ktmp, itmp, n, dim * B, s);
+  dev_release(ktmp, s);
+  dev_release(itmp, s);
+  if (e == hipSuccess)
+    e = gather_points(dim, xyz, n, t->st.id, n, t->st.X, t->st.Y, t->st.Z, t->slot_of, s);
+  if (e == hipSuccess) e = relink(t);
+  if (e != hipSuccess) {
+    destroy(t);
+    return to_status(e);
+  }
+  t->cap = n;
+  *out = t;
+  return ZD_OK;
+}
+
+zd_status zd_knn(zd_tree t, const double *q_xyz, int64_t m, int32_t k, int32_t *out_ids,
+                 double *out_d2, void *stream) {
+  if (!t || m < 0 || k < 1) return ZD_EINVAL;
+  if (k > ZD_KMAX) return ZD_EKMAX;
+  if (t->broken) return ZD_EDEVICE;
+  if (m > 0 && (!out_ids || !out_d2)) return ZD_EINVAL;
+  if (!q_xyz && m != t->cap) return ZD_EINVAL;
+  if (q_xyz && m > kMaxPoints) return ZD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = bind_stream(t, s);
+  if (e == hipSuccess && m > 0) {
+    if (!q_xyz) {
+      if (t->cap > t->st.n) e = fill_dead_rows(t->slot_of, t->cap, k, out_ids, out_d2, s);
+      if (e == hipSuccess) e = knn_all_points(t->dim, t->view(), k, out_ids, out_d2, s);
+    } else {
+      e = knn_external(t->dim, t->view(), t->geo, q_xyz, m, k, out_ids, out_d2, s);
+    }
+  }
+  if (e != hipSuccess) {
+    t->broken = e != hipErrorOutOfMemory;
+    return to_status(e);
+  }
+  return ZD_OK;
+}
+
+zd_status zd_insert_batch(zd_tree t, const double *xyz, int64_t m, int32_t *out_new_ids,
+                          void *stream) {
+  if (!t || m < 0) return ZD_EINVAL;
+  if (t->broken) return ZD_EDEVICE;
+  if (m == 0) return ZD_OK;
+  if (!xyz || t->cap + m > kMaxPoints) return ZD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int dim = t->dim;
+  hipError_t e = bind_stream(t, s);
+  // 1. validate the whole batch against the declared box
+  int32_t bad = 0;
+  if (e == hipSuccess) e = fill_i32(t->meta + kMetaErr, 0, 1, s);
+  if (e == hipSuccess) e = count_outside_box(dim, xyz, m, t->geo.lo, t->hi, t->meta + kMetaErr, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&bad, t->meta + kMetaErr, sizeof(bad), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    t->broken = true;
+    return to_status(e);
+  }
+  if (bad) return ZD_EBOUNDS;
+  // 2. key and sort the batch (Algorithm 4 starts from a shifted, sorted batch)
+  const int64_t n = t->st.n, n2 = n + m;
+  uint64_t *bk = nullptr, *bk2 = nullptr;
+  int32_t *bi = nullptr, *bi2 = nullptr, *src = nullptr, *scratch = nullptr;
+  Store next;
+  e = dev_alloc_n(&bk, m, s);
+  if (e == hipSuccess) e = dev_alloc_n(&bi, m, s);
+  if (e == hipSuccess) e = dev_alloc_n(&bk2, m, s);
+  if (e == hipSuccess) e = dev_alloc_n(&bi2, m, s);
+  if (e == hipSuccess) e = dev_alloc_n(&src, n2, s);
+  if (e == hipSuccess) e = dev_alloc_n(&scratch, 2 * n2, s);
+  if (e == hipSuccess) e = store_alloc(next, n2, dim, s);
+  if (e == hipSuccess) e = grow_ids(t, t->cap + m);
+  if (e != hipSuccess) {
+    // nothing changed yet: release and report
+    dev_release(bk, s); dev_release(bi, s); dev_release(bk2, s); dev_release(bi2, s);
+    dev_release(src, s); dev_release(scratch, s);
+    store_release(next, s);
+    return to_status(e);
+  }
+  e = encode_keys(t->geo, xyz, m, m, (int32_t)t->cap, bk, bi, s);
+  if (e == hipSuccess) e = radix_sort_pairs(bk, bi, bk2, bi2, m, dim * t->geo.B, s);
+  // 3. merge into the Morton-ordered points, 4. gather, 5. relink
+  if (e == hipSuccess)
+    e = merge_sorted(t->st.key, t->st.id, n, bk, bi, m, scratch, next.key, next.id, src, s);
+  if (e == hipSuccess)
+    e = gather_merged(dim, src, n2, t->st.X, t->st.Y, t->st.Z, xyz, m, (int32_t)t->cap, next.id,
+                      next.X, next.Y, next.Z, t->slot_of, s);
+  if (e == hipSuccess && out_new_ids) e = iota_i32(out_new_ids, (int32_t)t->cap, m, s);
+  dev_release(bk, s); dev_release(bi, s); dev_release(bk2, s); dev_release(bi2, s);
+  dev_release(src, s); dev_release(scratch, s);
+  if (e == hipSuccess) {
+    store_release(t->st, s);
+    t->st = next;
+    t->cap += m;
+    e = relink(t);
+  } else {
+    store_release(next, s);
+  }
+  if (e != hipSuccess) {
+    t->broken = true;
+    return to_status(e);
+  }
+  return ZD_OK;
+}
+
+zd_status zd_delete_batch(zd_tree t, const int32_t *ids, int64_t m, void *stream) {
+  if (!t || m < 0) return ZD_EINVAL;
+  if (t->broken) return ZD_EDEVICE;
+  if (m == 0) return ZD_OK;
+  if (!ids) return ZD_EINVAL;
+  if (m > t->st.n) return ZD_EID;
+  hipStream_t s = (hipStream_t)stream;
+  const int dim = t->dim;
+  hipError_t e = bind_stream(t, s);
+  // 1. validate: every id in range, live, and unique in the batch
+  int32_t bad = 0;
+  if (e == hipSuccess) e = fill_i32(t->meta + kMetaErr, 0, 1, s);
+  if (e == hipSuccess)
+    e = validate_delete(ids, m, t->cap, t->slot_of, t->mark, t->meta + kMetaErr, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&bad, t->meta + kMetaErr, sizeof(bad), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && bad) e = unmark_ids(ids, m, t->cap, t->mark, s);
+  if (e != hipSuccess) {
+    t->broken = true;
+    return to_status(e);
+  }
+  if (bad) return ZD_EID;
+  // 2. remove, 3. compact the survivors in Morton order, 4. relink
+  const int64_t n = t->st.n, n2 = n - m;
+  int32_t *dead = nullptr, *scan = nullptr;
+  Store next;
+  e = dev_alloc_n(&dead, n, s);
+  if (e == hipSuccess) e = dev_alloc_n(&scan, n, s);
+  if (e == hipSuccess) e = store_alloc(next, n2, dim, s);
+  if (e != hipSuccess) {
+    (void)unmark_ids(ids, m, t->cap, t->mark, s);
+    dev_release(dead, s); dev_release(scan, s);
+    store_release(next, s);
+    return to_status(e);
+  }
+  e = fill_i32(dead, 0, n, s);
+  if (e == hipSuccess) e = kill_ids(ids, m, t->slot_of, t->mark, dead, s);
+  if (e == hipSuccess)
+    e = compact_live(dim, dead, n, scan, t->st.key, t->st.id, t->st.X, t->st.Y, t->st.Z,
+                     next.key, next.id, next.X, next.Y, next.Z, t->slot_of, s);
+  dev_release(dead, s);
+  dev_release(scan, s);
+  if (e == hipSuccess) {
+    store_release(t->st, s);
+    t->st = next;
+    e = relink(t);
+  } else {
+    store_release(next, s);
+  }
+  if (e != hipSuccess) {
+    t->broken = true;
+    return to_status(e);
+  }
+  return ZD_OK;
+}
+
+zd_status zd_free(zd_tree t) {
+  destroy(t);
+  return ZD_OK;
+}
+
+zd_status zd_info(zd_tree t, int64_t *n_live, int64_t *id_capacity, int64_t *n_leaves,
+                  int64_t *n_internal) {
+  if (!t) return ZD_EINVAL;
+  int32_t I = 0;
+  if (t->st.n > 0) {
+    hipError_t e = hipMemcpyAsync(&I, t->meta + kMetaInternal, sizeof(I), hipMemcpyDeviceToHost,
+                                  t->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(t->stream);
+    if (e != hipSuccess) return to_status(e);
+  }
+  if (n_live) *n_live = t->st.n;
+  if (id_capacity) *id_capacity = t->cap;
+  if (n_leaves) *n_leaves = t->st.n > 0 ? (int64_t)I + 1 : 0;
+  if (n_internal) *n_internal = t->st.n > 0 ? I : 0;
+  return ZD_OK;
+}
+
+zd_status zd_export(zd_tree t, uint64_t *keys, int32_t *ids, int64_t *leaf_count,
+                    double *leaf_lo, double *leaf_hi, int32_t *int_bit, double *int_lo,
+                    double *int_hi, double *params_out, uint64_t *shift_out) {
+  if (!t) return ZD_EINVAL;
+  const int dim = t->dim;
+  if (params_out)
+    for (int c = 0; c < dim; ++c) {
+      params_out[c] = t->geo.lo[c];
+      params_out[dim + c] = t->hi[c];
+      params_out[2 * dim + c] = t->geo.S[c];
+    }
+  if (shift_out)
+    for (int c = 0; c < dim; ++c) shift_out[c] = t->geo.shift[c];
+  const int64_t n = t->st.n;
+  if (n == 0) return ZD_OK;
+  hipStream_t s = t->stream;
+  int32_t I = 0;
+  hipError_t e = hipMemcpyAsync(&I, t->meta + kMetaInternal, sizeof(I), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return to_status(e);
+  const int64_t nl = (int64_t)I + 1;
+  std::vector<int32_t> lb(nl + 1), lp(nl);
+  std::vector<INode> in((size_t)I);
+  double rb[6];
+  if (keys) e = hipMemcpyAsync(keys, t->st.key, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && ids)
+    e = hipMemcpyAsync(ids, t->st.id, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(lb.data(), t->st.leaf_begin, sizeof(int32_t) * (nl + 1),
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(lp.data(), t->st.leaf_parent, sizeof(int32_t) * nl, hipMemcpyDeviceToHost,
+                       s);
+  if (e == hipSuccess && I > 0)
+    e = hipMemcpyAsync(in.data(), t->st.inode, sizeof(INode) * (size_t)I, hipMemcpyDeviceToHost,
+                       s);
+  if (e == hipSuccess) e = hipMemcpyAsync(rb, t->root_box, sizeof(rb), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return to_status(e);
+  auto put_box = [&](double *lo, double *hi, int64_t row, int32_t link) {
+    for (int c = 0; c < dim; ++c) {
+      if (link < 0) {
+        if (lo) lo[row * dim + c] = rb[c];
+        if (hi) hi[row * dim + c] = rb[3 + c];
+      } else {
+        const INode &P = in[link >> 1];
+        if (lo) lo[row * dim + c] = P.lo[link & 1][c];
+        if (hi) hi[row * dim + c] = P.hi[link & 1][c];
+      }
+    }
+  };
+  for (int64_t j = 0; j < nl; ++j) {
+    if (leaf_count) leaf_count[j] = lb[j + 1] - lb[j];
+    put_box(leaf_lo, leaf_hi, j, lp[j]);
+  }
+  for (int64_t x = 0; x < I; ++x) {
+    if (int_bit) int_bit[x] = in[x].bit;
+    put_box(int_lo, int_hi, x, in[x].parent);
+  }
+  return ZD_OK;
+}
+
+zd_status zd_knn_backward(int32_t dim, const double *xyz, int64_t stride, int64_t rows,
+                          int32_t k, const int32_t *ids, const double *grad_d2, double *grad_xyz,
+                          void *stream) {
+  if ((dim != 2 && dim != 3) || stride < 0 || rows < 0 || rows > stride || k < 1) return ZD_EINVAL;
+  if (stride > 0 && (!xyz || !grad_xyz)) return ZD_EINVAL;
+  if (rows > 0 && (!ids || !grad_d2)) return ZD_EINVAL;
+  return to_status(
+      knn_backward(dim, xyz, stride, rows, k, ids, grad_d2, grad_xyz, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,229 @@
+// zd_build.hip -- zd-tree construction on gfx950.
+//
+// Algorithm 1 (buildTree) recurses top-down: a range of Morton-sorted points
+// with more than L points and distinct keys splits on its highest differing
+// key bit (found by binary search, splitUsingBit), and empty cuts are skipped
+// (Section 2.1).  The resulting tree is the binary radix (Patricia) tree of
+// the sorted keys, truncated at nodes of at most L points.  This file builds
+// the same tree bottom-up, with no recursion and a constant number of
+// launches:
+//
+//  1. encode:   per point, round to integer cells, add the shift, interleave.
+//  2. sort:     radix sort of (key, id)  (zd_sort.hip).
+//  3. gather:   coordinates into Morton order (structure of arrays), id map.
+//  4. flags:    sorted position i (between points i and i+1) carries the
+//               split of the radix node whose highest differing bit is
+//               bit(i) = highest bit of key[i] ^ key[i+1]; that node spans
+//               the maximal run of points around i sharing key[i]'s prefix
+//               above bit(i).  Position i is an internal zd-tree node iff
+//               the run holds more than L points (a bounded scan of at most
+//               L+1 neighbours each way decides it).
+//  5. compact:  scan the flags; internal node x = x-th flagged position,
+//               which is the in-order numbering of internal nodes.
+//  6. leaves:   in a full binary tree the in-order sequence alternates
+//               leaf, internal, ..., leaf, so leaf j is the run of points
+//               between internal positions j-1 and j.  One thread per leaf
+//               computes its tight box, then climbs: the parent of a node
+//               spanning leaves [l, r] is whichever neighbouring internal
+//               node (l-1 or r) splits on the lower bit.  Each parent's
+//               second arriving child merges the two boxes and continues,
+//               so every node is finished exactly once.
+#include "zd_internal.h"
+
+namespace zd {
+
+// ----------------------------------------------------------------- encode --
+
+template <int D>
+__global__ void k_encode(Geometry g, const double *__restrict__ xyz, int64_t stride, int64_t n,
+                         int32_t id_base, uint64_t *__restrict__ key, int32_t *__restrict__ id) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x = xyz[i], y = xyz[stride + i];
+  double z = D == 3 ? xyz[2 * stride + i] : 0.0;
+  key[i] = morton_key<D>(g, x, y, z);
+  id[i] = id_base + (int32_t)i;
+}
+
+hipError_t encode_keys(const Geometry &g, const double *xyz, int64_t stride, int64_t n,
+                       int32_t id_base, uint64_t *key, int32_t *id, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  unsigned grid = (unsigned)((n + 255) / 256);
+  if (g.dim == 3)
+    k_encode<3><<<grid, 256, 0, s>>>(g, xyz, stride, n, id_base, key, id);
+  else
+    k_encode<2><<<grid, 256, 0, s>>>(g, xyz, stride, n, id_base, key, id);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- gather --
+
+template <int D>
+__global__ void k_gather(const double *__restrict__ xyz, int64_t stride,
+                         const int32_t *__restrict__ id, int64_t n, double *__restrict__ X,
+                         double *__restrict__ Y, double *__restrict__ Z,
+                         int32_t *__restrict__ slot_of) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t src = id[i];
+  X[i] = xyz[src];
+  Y[i] = xyz[stride + src];
+  if (D == 3) Z[i] = xyz[2 * stride + src];
+  slot_of[src] = (int32_t)i;
+}
+
+hipError_t gather_points(int dim, const double *xyz, int64_t stride, const int32_t *id,
+                         int64_t n, double *X, double *Y, double *Z, int32_t *slot_of,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  unsigned grid = (unsigned)((n + 255) / 256);
+  if (dim == 3)
+    k_gather<3><<<grid, 256, 0, s>>>(xyz, stride, id, n, X, Y, Z, slot_of);
+  else
+    k_gather<2><<<grid, 256, 0, s>>>(xyz, stride, id, n, X, Y, Z, slot_of);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ flags --
+
+// keys a and b agree on every bit above `bit`
+__device__ __forceinline__ bool same_prefix(uint64_t a, uint64_t b, int bit) {
+  return bit >= 63 ? true : ((a ^ b) >> (bit + 1)) == 0;
+}
+
+__global__ void k_split_flags(const uint64_t *__restrict__ key, int64_t n, int L,
+                              int32_t *__restrict__ flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
+  const uint64_t ki = key[i];
+  const int b = split_bit(ki, key[i + 1]);
+  int32_t f = 0;
+  if (b >= 0) {
+    // points i and i+1 are on the two sides; extend each side while the keys
+    // keep the node's prefix, stopping as soon as more than L points are seen
+    int64_t left = 1, right = 1;
+    for (int64_t x = i - 1; x >= 0 && left + right <= L; --x) {
+      if (!same_prefix(key[x], ki, b)) break;
+      ++left;
+    }
+    for (int64_t x = i + 2; x < n && left + right <= L; ++x) {
+      if (!same_prefix(key[x], ki, b)) break;
+      ++right;
+    }
+    f = (left + right > L) ? 1 : 0;
+  }
+  flag[i] = f;
+}
+
+// ---------------------------------------------------------------- compact --
+
+__global__ void k_compact(const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
+                          const uint64_t *__restrict__ key, int64_t n, INode *__restrict__ inode) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1 || !flag[i]) return;
+  INode &N = inode[pos[i]];
+  N.split = (int32_t)i;
+  N.bit = split_bit(key[i], key[i + 1]);
+  N.visits = 0;
+  N.parent = -1;
+}
+
+// ------------------------------------------------- leaves + bottom-up links --
+
+template <int D>
+__global__ void k_leaves(const double *__restrict__ X, const double *__restrict__ Y,
+                         const double *__restrict__ Z, int64_t n, INode *inode, int32_t *meta,
+                         int32_t *__restrict__ leaf_begin, int32_t *leaf_parent,
+                         int32_t *__restrict__ leaf_of, double *root_box) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t I = meta[kMetaInternal];
+  if (j > I) return;
+  const int32_t begin = j == 0 ? 0 : inode[j - 1].split + 1;
+  const int32_t end = j == I ? (int32_t)n : inode[j].split + 1;
+  leaf_begin[j] = begin;
+  if (j == I) leaf_begin[I + 1] = (int32_t)n;
+  double lo[3] = {INFINITY, INFINITY, D == 3 ? INFINITY : 0.0};
+  double hi[3] = {-INFINITY, -INFINITY, D == 3 ? -INFINITY : 0.0};
+  for (int32_t s = begin; s < end; ++s) {
+    leaf_of[s] = (int32_t)j;
+    double x = X[s], y = Y[s];
+    lo[0] = fmin(lo[0], x); hi[0] = fmax(hi[0], x);
+    lo[1] = fmin(lo[1], y); hi[1] = fmax(hi[1], y);
+    if (D == 3) {
+      double z = Z[s];
+      lo[2] = fmin(lo[2], z); hi[2] = fmax(hi[2], z);
+    }
+  }
+  // climb
+  int32_t l = (int32_t)j, r = (int32_t)j;
+  int32_t node = ~(int32_t)j;
+  while (true) {
+    if (l == 0 && r == I) {
+      meta[kMetaRoot] = node;
+      if (node < 0) leaf_parent[~node] = -1;
+      else inode[node].parent = -1;
+      for (int c = 0; c < 3; ++c) { root_box[c] = lo[c]; root_box[3 + c] = hi[c]; }
+      break;
+    }
+    int32_t p;
+    int side;
+    if (l == 0) { p = r; side = 0; }
+    else if (r == I) { p = l - 1; side = 1; }
+    else {
+      side = inode[r].bit < inode[l - 1].bit ? 0 : 1;
+      p = side ? l - 1 : r;
+    }
+    INode *P = &inode[p];
+    for (int c = 0; c < 3; ++c) { P->lo[side][c] = lo[c]; P->hi[side][c] = hi[c]; }
+    P->child[side] = node;
+    if (side == 0) P->first_leaf = l; else P->last_leaf = r;
+    if (node < 0) leaf_parent[~node] = (p << 1) | side;
+    else inode[node].parent = (p << 1) | side;
+    __threadfence();
+    int old = atomicAdd(&P->visits, 1);
+    if (old == 0) break;  // the sibling finishes this node
+    __threadfence();
+    const int os = 1 - side;
+    volatile INode *V = P;
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = fmin(lo[c], V->lo[os][c]);
+      hi[c] = fmax(hi[c], V->hi[os][c]);
+    }
+    if (side == 0) r = V->last_leaf; else l = V->first_leaf;
+    node = p;
+  }
+}
+
+hipError_t build_tree_links(int dim, int leaf_size, int64_t n, const BuildBuffers &b,
+                            hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (n <= 0) {
+    e = fill_i32(b.meta, 0, 1, s);
+    if (e == hipSuccess) e = fill_i32(b.meta + kMetaRoot, kNoRoot, 1, s);
+    return e;
+  }
+  const unsigned grid_n = (unsigned)((n + 255) / 256);
+  if (n > 1) {
+    k_split_flags<<<grid_n, 256, 0, s>>>(b.key, n, leaf_size, b.flag);
+    e = hipGetLastError();
+    // exclusive positions overwrite leaf_of (free until the leaf pass)
+    if (e == hipSuccess)
+      e = exclusive_scan_i32(b.flag, b.leaf_of, n - 1, b.meta + kMetaInternal, s);
+    if (e == hipSuccess) {
+      k_compact<<<grid_n, 256, 0, s>>>(b.flag, b.leaf_of, b.key, n, b.inode);
+      e = hipGetLastError();
+    }
+  } else {
+    e = fill_i32(b.meta + kMetaInternal, 0, 1, s);
+  }
+  if (e != hipSuccess) return e;
+  if (dim == 3)
+    k_leaves<3><<<grid_n, 256, 0, s>>>(b.X, b.Y, b.Z, n, b.inode, b.meta, b.leaf_begin,
+                                      b.leaf_parent, b.leaf_of, b.root_box);
+  else
+    k_leaves<2><<<grid_n, 256, 0, s>>>(b.X, b.Y, b.Z, n, b.inode, b.meta, b.leaf_begin,
+                                      b.leaf_parent, b.leaf_of, b.root_box);
+  return hipGetLastError();
+}
+
+}  // namespace zd

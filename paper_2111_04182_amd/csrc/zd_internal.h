@@ -1,0 +1,264 @@
+// zd_internal.h -- internal types and device helpers of libzd (gfx950).
+//
+// Everything here is private to the library; the public interface is
+// include/zd.h.  All HIP sources are compiled with -ffp-contract=off so that
+// no multiply-add is ever fused: squared distances must round exactly as
+// ((dx*dx + dy*dy) + dz*dz) does in IEEE binary64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "zd.h"
+
+namespace zd {
+
+// ---------------------------------------------------------------------------
+// tree layout in device memory
+// ---------------------------------------------------------------------------
+
+// One internal node.  The tight boxes of BOTH children are stored in the
+// parent, so a single 128-byte line answers "which children does the ball
+// reach, and which is nearer" during the search (Algorithm 2 reads the two
+// children's boxes and centres together).
+//   child[s] >= 0 : internal node index;  child[s] < 0 : leaf ~child[s].
+//   parent        : (parent << 1) | side-in-parent, or -1 at the root.
+//   bit           : the Morton key bit the node splits on.
+//   split         : sorted position p; the left subtree ends at point p.
+//   first/last    : the node's leaves, inclusive.
+//   visits        : arrival counter of the bottom-up construction.
+struct alignas(128) INode {
+  double lo[2][3];
+  double hi[2][3];
+  int32_t child[2];
+  int32_t parent;
+  int32_t bit;
+  int32_t split;
+  int32_t first_leaf;
+  int32_t last_leaf;
+  int32_t visits;
+};
+static_assert(sizeof(INode) == 128, "INode must fill one cache line");
+
+constexpr int32_t kNoRoot = INT32_MIN;
+
+// Key geometry: rounding to integers (Section 3.1) and the random shift
+// (Section 2).  B = 64/dim bits per coordinate; the box maps onto the low
+// 2^(B-1) cells, the shift is < 2^(B-1).
+struct Geometry {
+  double lo[3];
+  double S[3];
+  uint64_t shift[3];
+  int32_t dim;
+  int32_t B;
+};
+
+// An axis-aligned box, passed to kernels by value.
+struct Box3 {
+  double lo[3];
+  double hi[3];
+};
+
+// Device view of a built tree, passed to kernels by value.
+struct TreeView {
+  const uint64_t *key;      // [n] Morton keys, ascending
+  const int32_t *id;        // [n] point id of each sorted position
+  const double *X, *Y, *Z;  // [n] coordinates in sorted order
+  const int32_t *leaf_of;   // [n] leaf holding each sorted position
+  const int32_t *leaf_begin;   // [n_leaves + 1]
+  const int32_t *leaf_parent;  // [n_leaves] (parent << 1) | side, -1 if root
+  const INode *inode;       // [n_internal]
+  const int32_t *meta;      // meta[0] = n_internal, meta[1] = root
+  int64_t n;
+};
+
+// meta[] slots
+enum { kMetaInternal = 0, kMetaRoot = 1, kMetaErr = 2, kMetaCount = 4 };
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+
+// highest set bit of a non-zero 64-bit value
+__device__ __forceinline__ int high_bit64(uint64_t v) { return 63 - __clzll((long long)v); }
+
+// Split bit between two sorted keys, -1 if equal.
+__device__ __forceinline__ int split_bit(uint64_t a, uint64_t b) {
+  uint64_t x = a ^ b;
+  return x ? high_bit64(x) : -1;
+}
+
+// One coordinate to its integer cell: u = (x - lo) * S, floor, clamp into
+// [0, 2^(B-1) - 1]; monotone non-decreasing in x (NaN goes to cell 0).
+__device__ __forceinline__ uint64_t cell_of(double x, double lo, double S, int B) {
+  const uint64_t top = (uint64_t(1) << (B - 1)) - 1;
+  double u = (x - lo) * S;
+  if (!(u >= 0.0)) return 0;
+  double f = floor(u);
+  if (f >= (double)top) return top;
+  return (uint64_t)f;
+}
+
+// Spread the low 21 bits of v so bit j lands at 3j (3-D interleave).
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffULL;
+  v = (v | (v << 32)) & 0x001f00000000ffffULL;
+  v = (v | (v << 16)) & 0x001f0000ff0000ffULL;
+  v = (v | (v << 8)) & 0x100f00f00f00f00fULL;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
+  v = (v | (v << 2)) & 0x1249249249249249ULL;
+  return v;
+}
+
+// Spread the low 32 bits of v so bit j lands at 2j (2-D interleave).
+__device__ __forceinline__ uint64_t spread2(uint64_t v) {
+  v &= 0xffffffffULL;
+  v = (v | (v << 16)) & 0x0000ffff0000ffffULL;
+  v = (v | (v << 8)) & 0x00ff00ff00ff00ffULL;
+  v = (v | (v << 4)) & 0x0f0f0f0f0f0f0f0fULL;
+  v = (v | (v << 2)) & 0x3333333333333333ULL;
+  v = (v | (v << 1)) & 0x5555555555555555ULL;
+  return v;
+}
+
+// Morton key (Section 1.1): bit j of coordinate c at key bit d*j + (d-1-c),
+// x most significant within each group.
+template <int D>
+__device__ __forceinline__ uint64_t morton_key(const Geometry &g, double x, double y, double z) {
+  if constexpr (D == 3) {
+    uint64_t cx = cell_of(x, g.lo[0], g.S[0], 21) + g.shift[0];
+    uint64_t cy = cell_of(y, g.lo[1], g.S[1], 21) + g.shift[1];
+    uint64_t cz = cell_of(z, g.lo[2], g.S[2], 21) + g.shift[2];
+    return (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
+  } else {
+    uint64_t cx = cell_of(x, g.lo[0], g.S[0], 32) + g.shift[0];
+    uint64_t cy = cell_of(y, g.lo[1], g.S[1], 32) + g.shift[1];
+    return (spread2(cx) << 1) | spread2(cy);
+  }
+}
+
+// Squared distance with the fixed evaluation order (no FMA: the sources are
+// built with -ffp-contract=off).
+template <int D>
+__device__ __forceinline__ double dist2(double px, double py, double pz, double qx, double qy,
+                                        double qz) {
+  double dx = px - qx;
+  double dy = py - qy;
+  double s = dx * dx + dy * dy;
+  if constexpr (D == 3) {
+    double dz = pz - qz;
+    s = s + dz * dz;
+  }
+  return s;
+}
+
+// Gap from p to [lo, hi] along one axis (0 inside).  Rounding is monotone, so
+// for any point q of the box fl(gap) <= |fl(p - q)|: the box distance never
+// exceeds a member's distance, and pruning with it is exact.
+__device__ __forceinline__ double axis_gap(double p, double lo, double hi) {
+  return p < lo ? lo - p : (p > hi ? p - hi : 0.0);
+}
+
+template <int D>
+__device__ __forceinline__ double box_dist2(double px, double py, double pz, const double *lo,
+                                            const double *hi) {
+  double tx = axis_gap(px, lo[0], hi[0]);
+  double ty = axis_gap(py, lo[1], hi[1]);
+  double s = tx * tx + ty * ty;
+  if constexpr (D == 3) {
+    double tz = axis_gap(pz, lo[2], hi[2]);
+    s = s + tz * tz;
+  }
+  return s;
+}
+
+// (d, i) < (e, j) in the order on (d2, id)
+__device__ __forceinline__ bool cand_lt(double d, int32_t i, double e, int32_t j) {
+  return d < e || (d == e && i < j);
+}
+
+// ---------------------------------------------------------------------------
+// host-side internals (implemented across the .hip files)
+// ---------------------------------------------------------------------------
+
+// device allocation ordered on a stream (pool-backed)
+hipError_t dev_alloc(void **p, size_t bytes, hipStream_t s);
+void dev_release(void *p, hipStream_t s);
+
+template <typename T>
+hipError_t dev_alloc_n(T **p, int64_t n, hipStream_t s) {
+  return dev_alloc(reinterpret_cast<void **>(p), sizeof(T) * (size_t)(n > 0 ? n : 1), s);
+}
+
+// fill kernels (used instead of hipMemsetAsync, which must not be recorded
+// in captured graphs)
+hipError_t fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+hipError_t fill_f64(double *p, double v, int64_t n, hipStream_t s);
+
+// exclusive prefix sum of int32 values; the total goes to *total (device)
+// when total != nullptr.  in and out may alias.
+hipError_t exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total,
+                              hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs by key bits [0, key_bits).
+// Sorted pairs end in (key, val); key_tmp/val_tmp are scratch of n entries.
+hipError_t radix_sort_pairs(uint64_t *key, int32_t *val, uint64_t *key_tmp, int32_t *val_tmp,
+                            int64_t n, int key_bits, hipStream_t s);
+
+// Build kernels.  n points sorted by key in (key, id); the tree arrays have
+// room for n leaves and n internal nodes.
+struct BuildBuffers {
+  uint64_t *key;
+  int32_t *id;
+  double *X, *Y, *Z;
+  int32_t *leaf_of;
+  int32_t *leaf_begin;
+  int32_t *leaf_parent;
+  INode *inode;
+  int32_t *meta;
+  double *root_box;  // [6]: lo[3], hi[3]
+  int32_t *flag;     // scratch [n]
+};
+hipError_t encode_keys(const Geometry &g, const double *xyz, int64_t stride, int64_t n,
+                       int32_t id_base, uint64_t *key, int32_t *id, hipStream_t s);
+hipError_t gather_points(int dim, const double *xyz, int64_t stride, const int32_t *id,
+                         int64_t n, double *X, double *Y, double *Z, int32_t *slot_of,
+                         hipStream_t s);
+hipError_t build_tree_links(int dim, int leaf_size, int64_t n, const BuildBuffers &b,
+                            hipStream_t s);
+
+// Queries
+hipError_t knn_all_points(int dim, const TreeView &t, int k, int32_t *out_ids, double *out_d2,
+                          hipStream_t s);
+hipError_t knn_external(int dim, const TreeView &t, const Geometry &g, const double *q,
+                        int64_t m, int k, int32_t *out_ids, double *out_d2, hipStream_t s);
+hipError_t fill_dead_rows(const int32_t *slot_of, int64_t cap, int k, int32_t *out_ids,
+                          double *out_d2, hipStream_t s);
+
+// Backward
+hipError_t knn_backward(int dim, const double *xyz, int64_t stride, int64_t rows, int k,
+                        const int32_t *ids, const double *g, double *grad, hipStream_t s);
+
+// Updates
+hipError_t count_outside_box(int dim, const double *xyz, int64_t m, const double *lo,
+                             const double *hi, int32_t *counter, hipStream_t s);
+hipError_t box_reduce(int dim, const double *xyz, int64_t n, double *out_lo_hi, hipStream_t s);
+hipError_t merge_sorted(const uint64_t *ka, const int32_t *ia, int64_t na, const uint64_t *kb,
+                        const int32_t *ib, int64_t nb, int32_t *mark_scratch, uint64_t *kout,
+                        int32_t *iout, int32_t *src, hipStream_t s);
+hipError_t gather_merged(int dim, const int32_t *src, int64_t n, const double *X, const double *Y,
+                         const double *Z, const double *bxyz, int64_t nb, int32_t id_base,
+                         const int32_t *iout, double *X2, double *Y2, double *Z2,
+                         int32_t *slot_of, hipStream_t s);
+hipError_t validate_delete(const int32_t *ids, int64_t m, int64_t cap, const int32_t *slot_of,
+                           int32_t *mark, int32_t *err, hipStream_t s);
+hipError_t unmark_ids(const int32_t *ids, int64_t m, int64_t cap, int32_t *mark, hipStream_t s);
+hipError_t kill_ids(const int32_t *ids, int64_t m, int32_t *slot_of, int32_t *mark,
+                    int32_t *dead_slot, hipStream_t s);
+hipError_t compact_live(int dim, const int32_t *dead_slot, int64_t n, int32_t *scan_scratch,
+                        const uint64_t *key, const int32_t *id, const double *X,
+                        const double *Y, const double *Z, uint64_t *key2, int32_t *id2,
+                        double *X2, double *Y2, double *Z2, int32_t *slot_of, hipStream_t s);
+hipError_t iota_i32(int32_t *p, int32_t base, int64_t n, hipStream_t s);
+
+}  // namespace zd

@@ -1,0 +1,137 @@
+// zd_sort.hip -- stable LSD radix sort of (Morton key, id) pairs.
+//
+// The Morton sort of Section 2 ("Construction"); the paper notes a radix sort
+// gives linear work (Section 2.1, Theorem 1).  Each pass handles 8 key bits
+// in three kernels: per-tile digit counts, an exclusive scan of the counts in
+// digit-major order (which gives every (digit, tile) its output base), and a
+// stable scatter.  Inside a tile, each 64-lane wavefront ranks 64 keys at a
+// time: eight ballots find the lanes holding the same digit, and a per-wave
+// digit counter in LDS carries the running rank across rounds, so equal keys
+// keep their input order (ties stay in ascending id order).
+#include "zd_internal.h"
+
+namespace zd {
+
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortThreads = 256;  // 4 wavefronts
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys
+constexpr int kWaveSpan = 64 * kSortItems;            // keys per wave per tile
+
+__device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) {
+  return (uint32_t)(k >> shift) & (kRadix - 1);
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_radix_count(const uint64_t *key, int64_t n,
+                                                              int shift, int32_t *counts,
+                                                              int ntiles) {
+  __shared__ int32_t hist[kRadix];
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+  for (int j = 0; j < kSortItems; ++j) {
+    int64_t i = base + (int64_t)j * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&hist[digit_of(key[i], shift)], 1);
+  }
+  __syncthreads();
+  counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = hist[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
+    const uint64_t *__restrict__ key_in, const int32_t *__restrict__ val_in,
+    uint64_t *__restrict__ key_out, int32_t *__restrict__ val_out, int64_t n, int shift,
+    const int32_t *__restrict__ offsets, int ntiles) {
+  __shared__ int32_t wcount[kSortWaves][kRadix];
+  __shared__ int32_t gbase[kRadix];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < kSortWaves; ++i) wcount[i][threadIdx.x] = 0;
+  __syncthreads();
+
+  const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)w * kWaveSpan;
+  const uint64_t lt_mask = lane ? (~0ULL >> (64 - lane)) : 0ULL;
+  uint64_t k[kSortItems];
+  int32_t v[kSortItems];
+  int32_t rank[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    int64_t i = base + r * 64 + lane;
+    bool valid = i < n;
+    k[r] = valid ? key_in[i] : 0;
+    v[r] = valid ? val_in[i] : 0;
+    uint32_t d = digit_of(k[r], shift);
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      bool bit = (d >> b) & 1u;
+      uint64_t bb = __ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    int lower = __popcll(m & lt_mask);
+    int cnt = __popcll(m);
+    int32_t before = valid ? wcount[w][d] : 0;
+    rank[r] = before + lower;
+    if (valid && lower == cnt - 1) wcount[w][d] = before + cnt;
+  }
+  __syncthreads();
+  {
+    const int d = threadIdx.x;
+    int32_t run = 0;
+#pragma unroll
+    for (int i = 0; i < kSortWaves; ++i) {
+      int32_t t = wcount[i][d];
+      wcount[i][d] = run;
+      run += t;
+    }
+    gbase[d] = offsets[(int64_t)d * ntiles + blockIdx.x];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    int64_t i = base + r * 64 + lane;
+    if (i < n) {
+      uint32_t d = digit_of(k[r], shift);
+      int64_t pos = (int64_t)gbase[d] + wcount[w][d] + rank[r];
+      key_out[pos] = k[r];
+      val_out[pos] = v[r];
+    }
+  }
+}
+
+hipError_t radix_sort_pairs(uint64_t *key, int32_t *val, uint64_t *key_tmp, int32_t *val_tmp,
+                            int64_t n, int key_bits, hipStream_t s) {
+  if (n <= 1) return hipSuccess;
+  const int ntiles = (int)((n + kSortTile - 1) / kSortTile);
+  const int64_t ncounts = (int64_t)kRadix * ntiles;
+  int32_t *counts = nullptr;
+  hipError_t e = dev_alloc_n(&counts, ncounts, s);
+  if (e != hipSuccess) return e;
+  uint64_t *ka = key, *kb = key_tmp;
+  int32_t *va = val, *vb = val_tmp;
+  int passes = 0;
+  for (int shift = 0; shift < key_bits && e == hipSuccess; shift += kRadixBits) {
+    k_radix_count<<<ntiles, kSortThreads, 0, s>>>(ka, n, shift, counts, ntiles);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = exclusive_scan_i32(counts, counts, ncounts, nullptr, s);
+    if (e == hipSuccess) {
+      k_radix_scatter<<<ntiles, kSortThreads, 0, s>>>(ka, va, kb, vb, n, shift, counts, ntiles);
+      e = hipGetLastError();
+    }
+    uint64_t *tk = ka; ka = kb; kb = tk;
+    int32_t *tv = va; va = vb; vb = tv;
+    ++passes;
+  }
+  if (e == hipSuccess && (passes & 1)) {
+    e = hipMemcpyAsync(key, ka, sizeof(uint64_t) * (size_t)n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(val, va, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s);
+  }
+  dev_release(counts, s);
+  return e;
+}
+
+}  // namespace zd

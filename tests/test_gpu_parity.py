@@ -1,0 +1,284 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Ids and squared distances must be bit-identical (neighbours are exact; d2 is
+evaluated in the same order with no fused operations on both sides).  Trees
+are compared in their canonical in-order form.  Structure tests come first:
+a tree that fails them stops the run before any query walks it.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.treecheck import check_tree
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2111_04182_amd as zd  # noqa: E402
+
+
+def dev(P):
+    return zd.soa(torch.from_numpy(np.asarray(P, dtype=np.float64)))
+
+
+def canon(ex, dim):
+    return dict(keys=ex["keys"], ids=ex["ids"], leaf_count=ex["leaf_count"],
+                leaf_lo=ex["leaf_lo"][:, :dim], leaf_hi=ex["leaf_hi"][:, :dim],
+                int_bit=ex["int_bit"], int_lo=ex["int_lo"][:, :dim], int_hi=ex["int_hi"][:, :dim])
+
+
+def assert_same_tree(gex, oex, dim, what=""):
+    a, b = canon(gex, dim), canon(oex, dim)
+    for key in a:
+        assert np.array_equal(a[key], b[key]), f"{what}: tree field {key} differs"
+
+
+def assert_same_rows(got, want, what=""):
+    gi, gd = (x.cpu().numpy() if hasattr(x, "cpu") else x for x in got)
+    wi, wd = want
+    if not np.array_equal(gi, wi):
+        bad = np.argwhere(gi != wi)[:5]
+        raise AssertionError(f"{what}: ids differ at {bad.tolist()}: "
+                             f"{[(gi[r, c], wi[r, c]) for r, c in bad]}")
+    assert np.array_equal(gd, wd), f"{what}: d2 differ"
+
+
+def datasets():
+    return [
+        ("uniform2d", W.uniform(4000, 2, 1), (np.zeros(2), np.ones(2))),
+        ("uniform3d", W.uniform(6000, 3, 2), (np.zeros(3), np.ones(3))),
+        ("grid2d", W.grid_points((50, 50), 4, 3), None),
+        ("grid3d", W.grid_points((14, 14, 14), 3, 4), None),
+        ("dups3d", W.with_duplicates(3000, 3, 300, 5), None),
+        ("dups2d", W.with_duplicates(2000, 2, 40, 6), None),
+        ("collinear3d", W.collinear(2500, 3, 7), None),
+        ("clustered3d", W.clustered_small(5000, 3, 8), None),
+        ("allequal3d", np.full((50, 3), 0.25), None),
+        ("single3d", W.uniform(1, 3, 9), None),
+        ("pair2d", W.uniform(2, 2, 10), None),
+    ]
+
+
+DATA = datasets()
+IDS = [d[0] for d in DATA]
+
+
+# ------------------------------------------------------------ structure ----
+
+@pytest.mark.parametrize("L", [1, 5, 16])
+@pytest.mark.parametrize("case", range(len(DATA)), ids=IDS)
+def test_tree_matches_oracle(case, L):
+    name, P, box = DATA[case]
+    dim = P.shape[1]
+    g = zd.ZdTree(dev(P), leaf_size=L, box=box, shift_seed=17)
+    gex = g.export()
+    o = oracle.Tree(P, L, box=box, seed=17)
+    oex = o.export()
+    lo, hi, S, sh = o.params()
+    assert np.array_equal(gex["params"], np.concatenate([lo, hi, S])), name
+    assert np.array_equal(gex["shift"], sh), name
+    check_tree(gex, P, L)
+    assert_same_tree(gex, oex, dim, name)
+    g.close()
+
+
+# ------------------------------------------------------- all-points rows ----
+
+@pytest.mark.parametrize("k", [1, 3, 10, 16, 24, 50, 64])
+@pytest.mark.parametrize("case", range(len(DATA)), ids=IDS)
+def test_all_points_match_oracle(case, k):
+    name, P, box = DATA[case]
+    g = zd.ZdTree(dev(P), leaf_size=16, box=box, shift_seed=3)
+    assert_same_rows(g.knn(k), oracle.brute_knn(P, k), f"{name} k={k}")
+    g.close()
+
+
+@pytest.mark.parametrize("L", [1, 2, 7, 32])
+def test_leaf_size_does_not_change_rows(L):
+    P = W.clustered_small(4000, 3, 11)
+    want = oracle.brute_knn(P, 12)
+    g = zd.ZdTree(dev(P), leaf_size=L, shift_seed=L)
+    assert_same_rows(g.knn(12), want, f"L={L}")
+    g.close()
+
+
+def test_config1_uniform2d_full():
+    P = W.cfg1_uniform2d()
+    g = zd.ZdTree(dev(P), leaf_size=16, box=W.UNIT2, shift_seed=0)
+    o = oracle.Tree(P, 16, box=W.UNIT2, seed=0)
+    assert_same_tree(g.export(), o.export(), 2, "config1")
+    assert_same_rows(g.knn(10), oracle.brute_knn(P, 10), "config1")
+    g.close()
+
+
+# -------------------------------------------------------- external rows ----
+
+@pytest.mark.parametrize("k", [1, 8, 16, 40])
+@pytest.mark.parametrize("case", [0, 1, 3, 4, 7], ids=[IDS[i] for i in (0, 1, 3, 4, 7)])
+def test_external_queries_match_oracle(case, k):
+    name, P, box = DATA[case]
+    dim = P.shape[1]
+    # queries inside and outside the data (outside the box is legal), plus copies of points
+    Q = np.concatenate([W.uniform(700, dim, 40 + case) * 1.2 - 0.1, P[:100]])
+    g = zd.ZdTree(dev(P), leaf_size=16, box=box, shift_seed=5)
+    assert_same_rows(g.knn(k, dev(Q)), oracle.brute_knn(P, k, queries=Q), f"{name} ext k={k}")
+    g.close()
+
+
+# --------------------------------------------------------------- updates ----
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("L", [1, 16])
+def test_update_sequence_matches_oracle(dim, L):
+    rng = np.random.default_rng(100 + dim + L)
+    box = (np.zeros(dim), np.ones(dim))
+    P = W.clustered_small(3000, dim, 101).clip(0, 1)
+    g = zd.ZdTree(dev(P), leaf_size=L, box=box, shift_seed=9)
+    o = oracle.Tree(P, L, box=box, seed=9)
+    allp = P.copy()
+    live = np.ones(len(P), dtype=bool)
+    for rnd in range(5):
+        Q = np.concatenate([rng.random((400, dim)),
+                            W.with_duplicates(50, dim, 4, 200 + rnd).clip(0, 1)])
+        new_g = g.insert(dev(Q)).cpu().numpy()
+        new_o = o.insert(Q)
+        assert np.array_equal(new_g, new_o)
+        allp = np.concatenate([allp, Q])
+        live = np.concatenate([live, np.ones(len(Q), dtype=bool)])
+        assert_same_tree(g.export(), o.export(), dim, f"after insert {rnd}")
+        D = rng.choice(np.flatnonzero(live), 450, replace=False).astype(np.int32)
+        g.delete(torch.from_numpy(D).cuda())
+        o.delete(D)
+        live[D] = False
+        gex = g.export()
+        check_tree(gex, allp, L, np.flatnonzero(live))
+        assert_same_tree(gex, o.export(), dim, f"after delete {rnd}")
+        assert_same_rows(g.knn(9), oracle.brute_knn(allp, 9, live=live), f"round {rnd}")
+    g.close()
+
+
+def test_empty_tree_then_insert():
+    box = W.UNIT3
+    g = zd.ZdTree(torch.zeros((3, 0), dtype=torch.float64, device="cuda"), 8, box=box)
+    assert g.info()["n_live"] == 0
+    ids, d2 = g.knn(4, dev(W.uniform(10, 3, 1)))
+    assert (ids.cpu().numpy() == -1).all() and np.isinf(d2.cpu().numpy()).all()
+    P = W.uniform(300, 3, 2)
+    g.insert(dev(P))
+    assert_same_rows(g.knn(4), oracle.brute_knn(P, 4), "after first insert")
+    g.delete(torch.arange(300, dtype=torch.int32, device="cuda"))
+    assert g.info()["n_live"] == 0
+    ids, _ = g.knn(4)
+    assert (ids.cpu().numpy() == -1).all()
+    g.close()
+
+
+def test_update_errors_leave_tree_unchanged():
+    P = W.uniform(2000, 3, 300)
+    g = zd.ZdTree(dev(P), 8, box=W.UNIT3, shift_seed=1)
+    before = g.export()
+    bad = W.uniform(100, 3, 301)
+    bad[42, 2] = 1.5
+    with pytest.raises(zd.ZdError) as e:
+        g.insert(dev(bad))
+    assert e.value.code == 2
+    for ids in ([1, 2, 2], [5, 2000], [-3], [7, 8, 10**7]):
+        with pytest.raises(zd.ZdError) as e:
+            g.delete(torch.tensor(ids, dtype=torch.int32))
+        assert e.value.code == 3
+    assert_same_tree(g.export(), before, 3, "after rejected updates")
+    g.delete(torch.tensor([11], dtype=torch.int32))
+    with pytest.raises(zd.ZdError) as e:
+        g.delete(torch.tensor([11], dtype=torch.int32))
+    assert e.value.code == 3
+    live = np.ones(2000, dtype=bool)
+    live[11] = False
+    assert_same_rows(g.knn(5), oracle.brute_knn(P, 5, live=live), "after delete")
+    g.close()
+
+
+def test_invalid_arguments():
+    P = dev(W.uniform(100, 3, 5))
+    with pytest.raises(zd.ZdError):
+        zd.ZdTree(P, leaf_size=0)
+    with pytest.raises(zd.ZdError):
+        zd.ZdTree(P, box=(np.zeros(3), np.array([1.0, 0.0, 1.0])))
+    g = zd.ZdTree(P, 4)
+    with pytest.raises(zd.ZdError) as e:
+        g.knn(65)
+    assert e.value.code == 6
+    g.close()
+
+
+# -------------------------------------------------------------- backward ----
+
+def test_backward_matches_closed_form_and_fd():
+    P = W.uniform(3000, 3, 400)
+    g = zd.ZdTree(dev(P), 16, box=W.UNIT3)
+    xyz = dev(P)
+    ids, d2 = g.knn(8)
+    w = torch.from_numpy(np.random.default_rng(401).uniform(0.5, 2, (3000, 8))).cuda()
+    grad = zd.zd_knn_backward(xyz, ids, w).cpu().numpy().T
+    ref = oracle.knn_grad(P, ids.cpu().numpy(), w.cpu().numpy())
+    scale = np.abs(ref).max()
+    assert np.abs(grad - ref).max() <= 1e-13 * max(scale, 1.0)
+    assert np.abs(grad.sum(axis=0)).max() < 1e-10
+    g.close()
+
+
+def test_autograd_function():
+    P = W.uniform(2000, 3, 410)
+    g = zd.ZdTree(dev(P), 16, box=W.UNIT3)
+    xyz = dev(P).requires_grad_(True)
+    d2, ids = zd.ZdKnnSqDist.apply(xyz, g, 6)
+    loss = d2.sum()
+    loss.backward()
+    ref = oracle.knn_grad(P, ids.cpu().numpy(), np.ones((2000, 6)))
+    assert np.allclose(xyz.grad.cpu().numpy().T, ref, rtol=1e-12, atol=1e-13)
+    g.close()
+
+
+# ---------------------------------------------------- full-size sampled ----
+
+@pytest.mark.timeout(600)
+def test_config2_full_size_sampled():
+    """3D uniform, n = 10M: tree equals the oracle's; sampled rows equal the
+    oracle's; then insert 1M, delete 1M, re-query (sampled)."""
+    P, Q, D = W.cfg2_uniform3d()
+    print("config2: building", flush=True)
+    g = zd.ZdTree(dev(P), 16, box=W.UNIT3, shift_seed=0)
+    o = oracle.Tree(P, 16, box=W.UNIT3, seed=0)
+    gex, oex = g.export(), o.export()
+    for key in ("keys", "ids", "leaf_count", "int_bit"):
+        assert np.array_equal(gex[key], oex[key]), key
+    ids, d2 = g.knn(10)
+    rows = np.random.default_rng(5).choice(len(P), 20000, replace=False)
+    want = o.knn_all(10, qids=rows)
+    assert_same_rows((ids[torch.from_numpy(rows).cuda()], d2[torch.from_numpy(rows).cuda()]), want,
+                     "config2 rows")
+    few = rows[:25]
+    assert_same_rows((ids[torch.from_numpy(few).cuda()], d2[torch.from_numpy(few).cuda()]),
+                     oracle.brute_knn(P, 10, qids=few), "config2 brute rows")
+    print("config2: updates", flush=True)
+    g.insert(dev(Q))
+    o.insert(Q)
+    g.delete(torch.from_numpy(D).cuda())
+    o.delete(D)
+    gex, oex = g.export(), o.export()
+    for key in ("keys", "ids", "leaf_count", "int_bit"):
+        assert np.array_equal(gex[key], oex[key]), key
+    ids, d2 = g.knn(10)
+    live = np.flatnonzero(~np.isin(np.arange(len(P) + len(Q)), D))
+    rows = np.random.default_rng(6).choice(live, 20000, replace=False)
+    want = o.knn_all(10, qids=rows)
+    assert_same_rows((ids[torch.from_numpy(rows).cuda()], d2[torch.from_numpy(rows).cuda()]), want,
+                     "config2 rows after updates")
+    dead = D[:100]
+    assert (ids[torch.from_numpy(dead).cuda()].cpu().numpy() == -1).all()
+    g.close()

@@ -1,0 +1,61 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/zd.h declares, and rejects bad arguments before it
+touches the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "zd.h")).read()
+    return re.findall(r"^ZD_API\s+[\w\s\*]+?\b(zd_\w+)\s*\(", src, flags=re.M)
+
+
+@pytest.fixture(scope="module")
+def L():
+    pytest.importorskip("torch")
+    import paper_2111_04182_amd as zd
+    return zd.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("zd_build", "zd_knn", "zd_insert_batch", "zd_delete_batch", "zd_free"):
+        assert n in names
+    assert len(names) == len(set(names))
+
+
+def test_library_exports_every_declared_symbol(L):
+    for n in declared_functions():
+        assert hasattr(L, n), n
+
+
+def test_status_strings(L):
+    for code in range(7):
+        assert L.zd_status_str(code)
+    assert L.zd_status_str(99) == b"unknown status"
+
+
+def test_argument_errors_need_no_device(L):
+    import paper_2111_04182_amd._lib as B
+    vp = C.c_void_p
+    out = vp()
+    assert L.zd_build(None, None, 0, None, C.byref(out)) == B.ZD_EINVAL
+    for dim, leaf, n in ((4, 16, 10), (1, 16, 10), (3, 0, 10), (3, 16, -1), (2, 16, 2**31)):
+        p = B._Params(dim, leaf, 0, None, None, None)
+        assert L.zd_build(C.byref(p), vp(1), n, None, C.byref(out)) == B.ZD_EINVAL
+    p = B._Params(3, 16, 0, None, None, None)
+    assert L.zd_build(C.byref(p), None, 0, None, C.byref(out)) == B.ZD_EINVAL  # n=0, no box
+    assert L.zd_build(C.byref(p), None, 5, None, C.byref(out)) == B.ZD_EINVAL  # NULL coords
+    assert L.zd_knn(None, None, 0, 1, None, None, None) == B.ZD_EINVAL
+    assert L.zd_insert_batch(None, None, 1, None, None) == B.ZD_EINVAL
+    assert L.zd_delete_batch(None, None, 1, None) == B.ZD_EINVAL
+    assert L.zd_info(None, None, None, None, None) == B.ZD_EINVAL
+    assert L.zd_free(None) == B.ZD_OK
+    assert L.zd_knn_backward(4, None, 0, 0, 1, None, None, None, None) == B.ZD_EINVAL
+    assert L.zd_knn_backward(3, None, 10, 20, 1, None, None, None, None) == B.ZD_EINVAL
+    assert out.value is None
