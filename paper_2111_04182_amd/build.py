@@ -17,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libzd.so")
 
-SOURCES = ["zd_scan.hip", "zd_sort.hip", "zd_build.hip", "zd_knn.hip", "zd_update.hip",
+SOURCES = ["zd_knn_all_d3.hip", "zd_knn_all_d2.hip", "zd_knn_ext_d3.hip", "zd_knn_ext_d2.hip",
+           "zd_scan.hip", "zd_sort.hip", "zd_build.hip", "zd_knn.hip", "zd_update.hip",
            "zd_grad.hip", "zd_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

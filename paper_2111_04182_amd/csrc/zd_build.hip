@@ -130,6 +130,19 @@ __global__ void k_compact(const int32_t *__restrict__ flag, const int32_t *__res
 
 // ------------------------------------------------- leaves + bottom-up links --
 
+// Values a child hands to its parent during the climb travel through device-
+// scope atomics only (64-bit exchanges to publish, no-op RMWs to read), which
+// are coherent across the chip's L2 slices; a __threadfence() here would write
+// back and invalidate the whole L2 at every step.
+__device__ __forceinline__ void publish_f64(double *p, double v) {
+  atomicExch(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
+}
+__device__ __forceinline__ double fetch_f64(double *p) {
+  return __longlong_as_double((long long)atomicOr(reinterpret_cast<unsigned long long *>(p), 0ULL));
+}
+__device__ __forceinline__ void publish_i32(int32_t *p, int32_t v) { atomicExch(p, v); }
+__device__ __forceinline__ int32_t fetch_i32(int32_t *p) { return atomicOr(p, 0); }
+
 template <int D>
 __global__ void k_leaves(const double *__restrict__ X, const double *__restrict__ Y,
                          const double *__restrict__ Z, int64_t n, INode *inode, int32_t *meta,
@@ -154,10 +167,11 @@ __global__ void k_leaves(const double *__restrict__ X, const double *__restrict_
       lo[2] = fmin(lo[2], z); hi[2] = fmax(hi[2], z);
     }
   }
-  // climb
+  // climb: a node spanning leaves [l, r] hangs below the neighbouring split
+  // (l-1 or r) with the lower bit
   int32_t l = (int32_t)j, r = (int32_t)j;
   int32_t node = ~(int32_t)j;
-  while (true) {
+  for (int guard = 0; guard < 130; ++guard) {
     if (l == 0 && r == I) {
       meta[kMetaRoot] = node;
       if (node < 0) leaf_parent[~node] = -1;
@@ -174,22 +188,30 @@ __global__ void k_leaves(const double *__restrict__ X, const double *__restrict_
       p = side ? l - 1 : r;
     }
     INode *P = &inode[p];
-    for (int c = 0; c < 3; ++c) { P->lo[side][c] = lo[c]; P->hi[side][c] = hi[c]; }
+    // links are read only by later kernels: plain stores
     P->child[side] = node;
-    if (side == 0) P->first_leaf = l; else P->last_leaf = r;
     if (node < 0) leaf_parent[~node] = (p << 1) | side;
     else inode[node].parent = (p << 1) | side;
-    __threadfence();
-    int old = atomicAdd(&P->visits, 1);
-    if (old == 0) break;  // the sibling finishes this node
-    __threadfence();
-    const int os = 1 - side;
-    volatile INode *V = P;
+    // what the sibling needs now: this child's box and outer bound
     for (int c = 0; c < 3; ++c) {
-      lo[c] = fmin(lo[c], V->lo[os][c]);
-      hi[c] = fmax(hi[c], V->hi[os][c]);
+      publish_f64(&P->lo[side][c], lo[c]);
+      publish_f64(&P->hi[side][c], hi[c]);
     }
-    if (side == 0) r = V->last_leaf; else l = V->first_leaf;
+    publish_i32(side == 0 ? &P->first_leaf : &P->last_leaf, side == 0 ? l : r);
+    // every publish has completed before the arrival is counted
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (atomicAdd(&P->visits, 1) == 0) break;  // the sibling finishes this node
+    const int os = 1 - side;
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = fmin(lo[c], fetch_f64(&P->lo[os][c]));
+      hi[c] = fmax(hi[c], fetch_f64(&P->hi[os][c]));
+    }
+    if (side == 0) r = fetch_i32(&P->last_leaf); else l = fetch_i32(&P->first_leaf);
+    // a corrupted exchange ends the climb instead of indexing out of range
+    if (l < 0 || r > I || l > r) {
+      atomicAdd(&meta[kMetaErr], 1);
+      break;
+    }
     node = p;
   }
 }

@@ -1,0 +1,18 @@
+// zd_knn_ext_d2.hip -- external-query search kernels for 2-D trees, one per k bucket.
+#include "zd_knn_impl.h"
+
+namespace zd {
+
+hipError_t knn_ext_d2(const TreeView &t, const double *q, const uint64_t *qkey,
+                      const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
+                      hipStream_t s) {
+  switch (k_bucket(k)) {
+#define X(KK) \
+  case KK: return launch_knn_ext<2, KK>(t, q, qkey, order, m, k, ids, d2, s);
+    ZD_FOR_EACH_K(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace zd

@@ -1,0 +1,367 @@
+// zd_knn_impl.h -- the exact k-NN search kernels (templates; instantiated in
+// zd_knn_d2.hip and zd_knn_d3.hip).
+//
+// Algorithm 3 (searchUp) scans the query's leaf, then climbs while the ball
+// of the current k-th distance leaves the current node's box, searching each
+// sibling subtree with Algorithm 2 (searchDown): a child is visited iff its
+// box distance is <= the k-th squared distance, nearer box centre first.
+//
+// On gfx950 a wavefront answers 64 queries that are consecutive in Morton
+// order (all-points rows in tree order; external queries after a Morton
+// presort, Section 3.1) with ONE shared walk:
+//   * the start node is the lowest common ancestor G of the group's leaves;
+//     searchDown runs over G's subtree, then the searchUp climb from G;
+//   * a child is visited when ANY lane's ball reaches it (a ballot of
+//     box distance <= that lane's k-th d2), and the climb stops once every
+//     lane's ball is inside the current box.  Each lane therefore sees a
+//     superset of the points its own search would see; since a lane only
+//     keeps its k smallest (d2, id), the rows are exact;
+//   * node records are read at wave-uniform addresses, and a visited leaf's
+//     points are staged once in LDS and broadcast to all lanes, so the walk
+//     itself never diverges;
+//   * for all-points rows, each lane first scores the group's own 64 points
+//     (its Morton neighbours), which tightens every lane's k-th distance
+//     before the walk starts; those positions are skipped later.
+#pragma once
+
+#include "zd_internal.h"
+
+#include <climits>
+
+namespace zd {
+
+// The candidate set N of Algorithms 2-3: the k best (d2, id) pairs so far,
+// ascending, in the LAST k of K registers; the first K-k hold (-inf, INT_MIN)
+// and never move.  So the k-th entry is always register K-1 and insertion is
+// a branch-free shift with static indices (no dynamic register indexing).
+// While fewer than k candidates have arrived the k-th entry is (+inf,
+// INT_MAX): distance(p, N, k) is infinite and every candidate enters.
+template <int K>
+struct Heap {
+  double d[K];
+  int32_t id[K];
+
+  __device__ __forceinline__ void init(int k) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const bool used = j >= K - k;
+      d[j] = used ? INFINITY : -INFINITY;
+      id[j] = used ? INT_MAX : INT_MIN;
+    }
+  }
+
+  __device__ __forceinline__ double kth() const { return d[K - 1]; }
+
+  // insert(N, q, k) of Algorithms 2-3: enters iff it precedes the k-th entry
+  __device__ __forceinline__ void offer(double dd, int32_t q) {
+    if (!cand_lt(dd, q, d[K - 1], id[K - 1])) return;
+    bool lt[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) lt[j] = cand_lt(dd, q, d[j], id[j]);
+#pragma unroll
+    for (int j = K - 1; j > 0; --j) {
+      // slot j takes its left neighbour if the candidate precedes that
+      // neighbour, else the candidate if it precedes slot j, else stays
+      const double nd = lt[j - 1] ? d[j - 1] : (lt[j] ? dd : d[j]);
+      const int32_t ni = lt[j - 1] ? id[j - 1] : (lt[j] ? q : id[j]);
+      d[j] = nd;
+      id[j] = ni;
+    }
+    if (lt[0]) {
+      d[0] = dd;
+      id[0] = q;
+    }
+  }
+
+  __device__ __forceinline__ void write(int k, int32_t *out_ids, double *out_d2) const {
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if (j >= K - k) {
+        const int o = j - (K - k);
+        out_ids[o] = id[j] == INT_MAX ? -1 : id[j];
+        out_d2[o] = d[j];
+      }
+  }
+};
+
+template <int D>
+__device__ __forceinline__ double centre_dist2(double px, double py, double pz, const double *lo,
+                                               const double *hi) {
+  const double cx = (lo[0] + hi[0]) * 0.5;
+  const double cy = (lo[1] + hi[1]) * 0.5;
+  const double cz = D == 3 ? (lo[2] + hi[2]) * 0.5 : 0.0;
+  return dist2<D>(px, py, pz, cx, cy, cz);
+}
+
+// withinBox(C, p, -r) of Algorithm 3, squared: p in the box and every face
+// strictly farther than the k-th d2 (never true while N holds fewer than k,
+// because the k-th d2 is then +inf).
+template <int D>
+__device__ __forceinline__ bool ball_inside(double px, double py, double pz, const double *lo,
+                                            const double *hi, double kth) {
+  const double p[3] = {px, py, pz};
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    if (p[c] < lo[c] || p[c] > hi[c]) return false;
+    const double a = p[c] - lo[c], b = hi[c] - p[c];
+    if (!(a * a > kth) || !(b * b > kth)) return false;
+  }
+  return true;
+}
+
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// one staged candidate point (32 bytes: two 16-byte LDS reads)
+struct Cand {
+  double x, y, z;
+  int32_t id;
+  int32_t pad;
+};
+
+// The per-lane state of one wavefront's shared search.
+template <int D, int K>
+struct WaveSearch {
+  const TreeView &t;
+  Cand *stage;                   // this wavefront's 64-entry LDS slice
+  double px, py, pz;             // this lane's query
+  double rx, ry, rz;             // group reference point (child order only)
+  int32_t self;                  // excluded id (-1 for external queries)
+  bool valid;                    // lane holds a query
+  int32_t skip_lo, skip_hi;      // sorted positions already scored
+  int64_t budget;                // walk bound (never reached on a valid tree)
+  Heap<K> h;
+
+  __device__ __forceinline__ WaveSearch(const TreeView &t_, Cand *stage_) : t(t_), stage(stage_) {}
+
+  __device__ __forceinline__ bool wants(const double *lo, const double *hi) const {
+    const bool w = valid && box_dist2<D>(px, py, pz, lo, hi) <= h.kth();
+    return __ballot(w) != 0;
+  }
+
+  // every lane scores every point of the leaf (except already-scored ones)
+  __device__ __forceinline__ void scan_leaf(int32_t leaf) {
+    const int lane = threadIdx.x & 63;
+    const int32_t b = uni(t.leaf_begin[leaf]), e = uni(t.leaf_begin[leaf + 1]);
+    for (int32_t c = b; c < e; c += 64) {
+      const int32_t j = c + lane;
+      if (j < e) {
+        Cand q;
+        q.x = t.X[j];
+        q.y = t.Y[j];
+        q.z = D == 3 ? t.Z[j] : 0.0;
+        q.id = t.id[j];
+        q.pad = 0;
+        stage[lane] = q;
+      }
+      __builtin_amdgcn_wave_barrier();
+      const int32_t cnt = min(64, e - c);
+      for (int32_t jj = 0; jj < cnt; ++jj) {
+        if (c + jj >= skip_lo && c + jj <= skip_hi) continue;
+        const Cand q = stage[jj];
+        const double dd = dist2<D>(px, py, pz, q.x, q.y, q.z);
+        if (valid && q.id != self) h.offer(dd, q.id);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+
+  // searchDown (Algorithm 2) below internal node `top`, whose own box the
+  // caller has already tested.  Stackless: nodes record parent and side, and
+  // the child order is recomputed when the walk returns to a node.
+  __device__ __forceinline__ void search_down(int32_t top) {
+    int32_t n = top;
+    bool entering = true;
+    int from_side = 0;
+    while (--budget > 0) {
+      const INode *N = &t.inode[n];
+      const double c0 = centre_dist2<D>(rx, ry, rz, N->lo[0], N->hi[0]);
+      const double c1 = centre_dist2<D>(rx, ry, rz, N->lo[1], N->hi[1]);
+      const int first = uni(c0 < c1 ? 0 : 1);
+      int s = entering ? first : (from_side == first ? 1 - first : 2);
+      bool descended = false;
+      while (s != 2) {
+        if (wants(N->lo[s], N->hi[s])) {
+          const int32_t ch = uni(N->child[s]);
+          if (ch < 0) {
+            scan_leaf(~ch);
+          } else {
+            n = ch;
+            entering = true;
+            descended = true;
+            break;
+          }
+        }
+        s = (s == first) ? 1 - first : 2;
+      }
+      if (descended) continue;
+      if (n == top) return;
+      const int32_t par = uni(N->parent);
+      if (par < 0) return;
+      from_side = par & 1;
+      n = par >> 1;
+      entering = false;
+    }
+  }
+
+  // the subtree of G (internal node, or leaf ~G), then the climb from G
+  __device__ __forceinline__ void run_from(int32_t G) {
+    int32_t link;
+    if (G < 0) {
+      scan_leaf(~G);
+      link = uni(t.leaf_parent[~G]);
+    } else {
+      search_down(G);
+      link = uni(t.inode[G].parent);
+    }
+    while (link >= 0 && --budget > 0) {
+      const int32_t p = link >> 1;
+      const int side = link & 1;
+      const INode *P = &t.inode[p];
+      const bool out = valid && !ball_inside<D>(px, py, pz, P->lo[side], P->hi[side], h.kth());
+      if (__ballot(out) == 0) break;
+      const int os = 1 - side;
+      if (wants(P->lo[os], P->hi[os])) {
+        const int32_t ch = uni(P->child[os]);
+        if (ch < 0) scan_leaf(~ch);
+        else search_down(ch);
+      }
+      link = uni(P->parent);
+    }
+  }
+};
+
+// All-points rows: wavefront w answers sorted positions [64w, 64w + 64).
+template <int D, int K>
+__global__ void __launch_bounds__(256) k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
+                                                 double *__restrict__ out_d2) {
+  __shared__ Cand stage_all[4][64];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int64_t g0 = ((int64_t)blockIdx.x * 4 + w) * 64;
+  if (g0 >= t.n) return;
+  const int64_t last = min(g0 + 63, t.n - 1);
+  const int64_t i = min(g0 + lane, last);
+  WaveSearch<D, K> s(t, stage_all[w]);
+  s.valid = g0 + lane <= last;
+  s.px = t.X[i];
+  s.py = t.Y[i];
+  s.pz = D == 3 ? t.Z[i] : 0.0;
+  s.self = t.id[i];
+  const int mid = (int)((last - g0) / 2);
+  s.rx = __shfl(s.px, mid, 64);
+  s.ry = __shfl(s.py, mid, 64);
+  s.rz = __shfl(s.pz, mid, 64);
+  s.budget = 4 * t.n + 256;
+  s.h.init(k);
+  // score the group's own points first (Morton neighbours of every lane)
+  {
+    Cand q;
+    q.x = s.px;
+    q.y = s.py;
+    q.z = s.pz;
+    q.id = s.self;
+    q.pad = 0;
+    s.stage[lane] = q;
+    __builtin_amdgcn_wave_barrier();
+    const int cnt = (int)(last - g0 + 1);
+    for (int jj = 0; jj < cnt; ++jj) {
+      const Cand c = s.stage[jj];
+      const double dd = dist2<D>(s.px, s.py, s.pz, c.x, c.y, c.z);
+      if (s.valid && jj != lane) s.h.offer(dd, c.id);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  s.skip_lo = (int32_t)g0;
+  s.skip_hi = (int32_t)last;
+  // lowest common ancestor of the group's leaves
+  const int32_t lf = uni(t.leaf_of[g0]), ll = uni(t.leaf_of[last]);
+  int32_t G = ~lf;
+  if (lf != ll) {
+    int32_t x = uni(t.leaf_parent[lf]) >> 1;
+    for (int guard = 0; guard < 130 && uni(t.inode[x].last_leaf) < ll; ++guard) {
+      const int32_t par = uni(t.inode[x].parent);
+      if (par < 0) break;
+      x = par >> 1;
+    }
+    G = x;
+  }
+  s.run_from(G);
+  if (s.valid) s.h.write(k, out_ids + (int64_t)s.self * k, out_d2 + (int64_t)s.self * k);
+}
+
+// External rows: wavefront w answers the Morton-sorted queries
+// order[64w .. 64w + 64); row r of the output belongs to query r.
+template <int D, int K>
+__global__ void __launch_bounds__(256) k_knn_ext(TreeView t, const double *__restrict__ q,
+                                                 const uint64_t *__restrict__ qkey,
+                                                 const int32_t *__restrict__ order, int64_t m,
+                                                 int k, int32_t *__restrict__ out_ids,
+                                                 double *__restrict__ out_d2) {
+  __shared__ Cand stage_all[4][64];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int64_t g0 = ((int64_t)blockIdx.x * 4 + w) * 64;
+  if (g0 >= m) return;
+  const int64_t last = min(g0 + 63, m - 1);
+  const int64_t i = min(g0 + lane, last);
+  const int32_t r = order[i];
+  WaveSearch<D, K> s(t, stage_all[w]);
+  s.valid = g0 + lane <= last;
+  s.px = q[r];
+  s.py = q[m + r];
+  s.pz = D == 3 ? q[2 * m + r] : 0.0;
+  s.self = -1;
+  const int mid = (int)((last - g0) / 2);
+  s.rx = __shfl(s.px, mid, 64);
+  s.ry = __shfl(s.py, mid, 64);
+  s.rz = __shfl(s.pz, mid, 64);
+  s.budget = 4 * t.n + 256;
+  s.skip_lo = 1;
+  s.skip_hi = 0;
+  s.h.init(k);
+  int32_t node = uni(t.meta[kMetaRoot]);
+  if (node != kNoRoot) {
+    // descend by the Morton bits (the bit-based search of Section 2) with the
+    // group's first and last keys; where they part, every key of the sorted
+    // group is below: that node is the group's common ancestor
+    const uint64_t k0 = qkey[g0], k1 = qkey[last];
+    for (int guard = 0; node >= 0 && guard < 66; ++guard) {
+      const INode *N = &t.inode[node];
+      const int bit = uni(N->bit);
+      const int b0 = (int)((k0 >> bit) & 1), b1 = (int)((k1 >> bit) & 1);
+      if (b0 != b1) break;
+      node = uni(N->child[b0]);
+    }
+    s.run_from(node);
+  }
+  if (s.valid) s.h.write(k, out_ids + (int64_t)r * k, out_d2 + (int64_t)r * k);
+}
+
+template <int D, int K>
+hipError_t launch_knn_all(const TreeView &t, int k, int32_t *ids, double *d2, hipStream_t s) {
+  const int64_t waves = (t.n + 63) / 64;
+  k_knn_all<D, K><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(t, k, ids, d2);
+  return hipGetLastError();
+}
+
+template <int D, int K>
+hipError_t launch_knn_ext(const TreeView &t, const double *q, const uint64_t *qkey,
+                          const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
+                          hipStream_t s) {
+  const int64_t waves = (m + 63) / 64;
+  k_knn_ext<D, K><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(t, q, qkey, order, m, k, ids, d2);
+  return hipGetLastError();
+}
+
+// K buckets: a k between two buckets runs in the larger one (the padding
+// slots cost registers, not correctness)
+#define ZD_FOR_EACH_K(X) X(1) X(2) X(4) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(50) X(64)
+
+inline int k_bucket(int k) {
+  const int b[] = {1, 2, 4, 8, 10, 12, 16, 20, 24, 32, 40, 50, 64};
+  for (int x : b)
+    if (k <= x) return x;
+  return 64;
+}
+
+}  // namespace zd
