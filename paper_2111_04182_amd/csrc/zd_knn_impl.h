@@ -1,10 +1,10 @@
-// zd_knn_impl.h -- the exact k-NN search kernels (templates; instantiated in
-// zd_knn_d2.hip and zd_knn_d3.hip).
+// zd_knn_impl.h -- the exact k-NN search kernels (templates; instantiated per
+// dimension and k bucket in zd_knn_all_d{2,3}.hip and zd_knn_ext_d{2,3}.hip).
 //
 // Algorithm 3 (searchUp) scans the query's leaf, then climbs while the ball
 // of the current k-th distance leaves the current node's box, searching each
 // sibling subtree with Algorithm 2 (searchDown): a child is visited iff its
-// box distance is <= the k-th squared distance, nearer box centre first.
+// box distance is <= the k-th squared distance, nearer child first.
 //
 // On gfx950 a wavefront answers 64 queries that are consecutive in Morton
 // order (all-points rows in tree order; external queries after a Morton
@@ -16,6 +16,9 @@
 //     lane's ball is inside the current box.  Each lane therefore sees a
 //     superset of the points its own search would see; since a lane only
 //     keeps its k smallest (d2, id), the rows are exact;
+//   * the nearer child is taken first (Algorithm 2's order heuristic), judged
+//     by the side of the split holding the Morton cell of the group's middle
+//     query: one integer test per node instead of two box-centre distances;
 //   * node records are read at wave-uniform addresses, and a visited leaf's
 //     points are staged once in LDS and broadcast to all lanes, so the walk
 //     itself never diverges;
@@ -84,15 +87,6 @@ struct Heap {
   }
 };
 
-template <int D>
-__device__ __forceinline__ double centre_dist2(double px, double py, double pz, const double *lo,
-                                               const double *hi) {
-  const double cx = (lo[0] + hi[0]) * 0.5;
-  const double cy = (lo[1] + hi[1]) * 0.5;
-  const double cz = D == 3 ? (lo[2] + hi[2]) * 0.5 : 0.0;
-  return dist2<D>(px, py, pz, cx, cy, cz);
-}
-
 // withinBox(C, p, -r) of Algorithm 3, squared: p in the box and every face
 // strictly farther than the k-th d2 (never true while N holds fewer than k,
 // because the k-th d2 is then +inf).
@@ -124,13 +118,12 @@ struct WaveSearch {
   const TreeView &t;
   Cand *stage;                   // this wavefront's 64-entry LDS slice
   double px, py, pz;             // this lane's query
-  double rx, ry, rz;             // group reference point (child order only)
   int32_t self;                  // excluded id (-1 for external queries)
   bool valid;                    // lane holds a query
   int32_t skip_lo, skip_hi;      // sorted positions already scored
   int64_t budget;                // walk bound (never reached on a valid tree)
+  uint64_t key_ref;              // Morton key of the group's middle query (child order)
   Heap<K> h;
-
   __device__ __forceinline__ WaveSearch(const TreeView &t_, Cand *stage_) : t(t_), stage(stage_) {}
 
   __device__ __forceinline__ bool wants(const double *lo, const double *hi) const {
@@ -174,9 +167,10 @@ struct WaveSearch {
     int from_side = 0;
     while (--budget > 0) {
       const INode *N = &t.inode[n];
-      const double c0 = centre_dist2<D>(rx, ry, rz, N->lo[0], N->hi[0]);
-      const double c1 = centre_dist2<D>(rx, ry, rz, N->lo[1], N->hi[1]);
-      const int first = uni(c0 < c1 ? 0 : 1);
+      // nearer child first: the side of the split holding the reference
+      // point's cell (an order heuristic only; it never changes the rows)
+      const int bit = uni(N->bit);
+      const int first = bit < 64 ? (int)((key_ref >> bit) & 1) : 0;
       int s = entering ? first : (from_side == first ? 1 - first : 2);
       bool descended = false;
       while (s != 2) {
@@ -248,10 +242,9 @@ __global__ void __launch_bounds__(256) k_knn_all(TreeView t, int k, int32_t *__r
   s.pz = D == 3 ? t.Z[i] : 0.0;
   s.self = t.id[i];
   const int mid = (int)((last - g0) / 2);
-  s.rx = __shfl(s.px, mid, 64);
-  s.ry = __shfl(s.py, mid, 64);
-  s.rz = __shfl(s.pz, mid, 64);
   s.budget = 4 * t.n + 256;
+  s.key_ref = uni((int32_t)(t.key[g0 + mid] >> 32));
+  s.key_ref = (s.key_ref << 32) | (uint32_t)uni((int32_t)t.key[g0 + mid]);
   s.h.init(k);
   // score the group's own points first (Morton neighbours of every lane)
   {
@@ -312,12 +305,11 @@ __global__ void __launch_bounds__(256) k_knn_ext(TreeView t, const double *__res
   s.pz = D == 3 ? q[2 * m + r] : 0.0;
   s.self = -1;
   const int mid = (int)((last - g0) / 2);
-  s.rx = __shfl(s.px, mid, 64);
-  s.ry = __shfl(s.py, mid, 64);
-  s.rz = __shfl(s.pz, mid, 64);
   s.budget = 4 * t.n + 256;
   s.skip_lo = 1;
   s.skip_hi = 0;
+  s.key_ref = uni((int32_t)(qkey[g0 + mid] >> 32));
+  s.key_ref = (s.key_ref << 32) | (uint32_t)uni((int32_t)qkey[g0 + mid]);
   s.h.init(k);
   int32_t node = uni(t.meta[kMetaRoot]);
   if (node != kNoRoot) {
