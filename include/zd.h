@@ -170,6 +170,47 @@ ZD_API zd_status zd_knn_backward(int32_t dim, const double *xyz, int64_t stride,
                           const double *grad_d2, double *grad_xyz,
                           void *stream);
 
+/* Batched forest: C independent point clouds answered in one pass (an
+ * addition beyond the paper, which builds one tree).  Cloud c is points
+ * [offsets[c], offsets[c+1]) of xyz; point i keeps id i.  Every cloud gets
+ * the tree a separate zd_build would give it (its own bounding cube unless
+ * params->box_lo/hi declare one box for all, the params' shift, and leaf
+ * size leaf_sizes[c], or params->leaf_size when leaf_sizes is NULL); the
+ * clouds share one device tree whose top levels separate them, and
+ * neighbours only ever come from the query's own cloud.
+ *   xyz: (device) SoA [dim][n].  offsets: (host) [n_clouds + 1], offsets[0]
+ *   = 0, non-decreasing, offsets[n_clouds] = n.  leaf_sizes: (host)
+ *   [n_clouds] or NULL.
+ * zd_forest_build runs build passes on `stream` and returns; it synchronises
+ * once to upload its tile and group tables.  Errors: ZD_EINVAL (as zd_build,
+ * plus bad offsets or leaf sizes), ZD_ENOMEM, ZD_EDEVICE. */
+ZD_API zd_status zd_forest_build(const zd_params *params, const double *xyz, int64_t n,
+                                 const int64_t *offsets, int32_t n_clouds,
+                                 const int32_t *leaf_sizes, void *stream, zd_forest *out);
+
+/* All-points k-NN rows of every cloud: row i (i < n) holds the k nearest
+ * points of point i's cloud other than i, as zd_knn.  out_ids/out_d2:
+ * (device) [n][k].  Asynchronous.  Errors: ZD_EINVAL, ZD_EKMAX, ZD_EDEVICE. */
+ZD_API zd_status zd_forest_knn(zd_forest forest, int32_t k, int32_t *out_ids, double *out_d2,
+                               void *stream);
+
+/* A forest whose whole build + all-points query is captured once into a
+ * HIP graph: zd_forest_run then rebuilds every tree from the current
+ * contents of xyz and writes the rows to out_ids/out_d2 with one graph
+ * launch, with no allocation and no host synchronisation.  The pointers
+ * xyz, out_ids and out_d2 are bound at plan time and must stay valid.
+ * zd_forest_plan synchronises `stream` (allocation, table upload, capture).
+ * Errors: as zd_forest_build and zd_forest_knn. */
+ZD_API zd_status zd_forest_plan(const zd_params *params, const double *xyz, int64_t n,
+                                const int64_t *offsets, int32_t n_clouds,
+                                const int32_t *leaf_sizes, int32_t k, int32_t *out_ids,
+                                double *out_d2, void *stream, zd_forest *out);
+ZD_API zd_status zd_forest_run(zd_forest forest, void *stream);
+
+/* Release a forest (after its work on the last stream used; a plan's graph
+ * and scratch are released after synchronising that stream). */
+ZD_API zd_status zd_forest_free(zd_forest forest);
+
 /* A short English description of a status code (static storage). */
 ZD_API const char *zd_status_str(zd_status status);
 

@@ -21,7 +21,8 @@ ZD_OK, ZD_EINVAL, ZD_EBOUNDS, ZD_EID, ZD_ENOMEM, ZD_EDEVICE, ZD_EKMAX = range(7)
 ZD_KMAX = 64
 
 EXPORTED = ("zd_build", "zd_knn", "zd_insert_batch", "zd_delete_batch", "zd_free", "zd_info",
-            "zd_export", "zd_knn_backward", "zd_status_str")
+            "zd_export", "zd_knn_backward", "zd_forest_build", "zd_forest_knn", "zd_forest_plan",
+            "zd_forest_run", "zd_forest_free", "zd_status_str")
 
 
 class ZdError(RuntimeError):
@@ -66,6 +67,17 @@ def lib() -> C.CDLL:
         L.zd_export.argtypes = [vp] * 11
         L.zd_knn_backward.restype = C.c_int
         L.zd_knn_backward.argtypes = [i32, vp, i64, i64, i32, vp, vp, vp, vp]
+        L.zd_forest_build.restype = C.c_int
+        L.zd_forest_build.argtypes = [C.POINTER(_Params), vp, i64, vp, i32, vp, vp, C.POINTER(vp)]
+        L.zd_forest_knn.restype = C.c_int
+        L.zd_forest_knn.argtypes = [vp, i32, vp, vp, vp]
+        L.zd_forest_plan.restype = C.c_int
+        L.zd_forest_plan.argtypes = [C.POINTER(_Params), vp, i64, vp, i32, vp, i32, vp, vp, vp,
+                                     C.POINTER(vp)]
+        L.zd_forest_run.restype = C.c_int
+        L.zd_forest_run.argtypes = [vp, vp]
+        L.zd_forest_free.restype = C.c_int
+        L.zd_forest_free.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -240,6 +252,118 @@ class ZdTree:
     def close(self):
         if getattr(self, "_h", None):
             zd_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------------------
+# batched forest
+# --------------------------------------------------------------------------
+
+def _forest_args(xyz, offsets, leaf_size, leaf_sizes, box, shift_seed, shift):
+    _check_soa(xyz)
+    dim, n = xyz.shape
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    ls = None if leaf_sizes is None else np.ascontiguousarray(leaf_sizes, dtype=np.int32)
+    lo = hi = sh = None
+    if box is not None:
+        lo = np.ascontiguousarray(box[0], dtype=np.float64)
+        hi = np.ascontiguousarray(box[1], dtype=np.float64)
+    if shift is not None:
+        sh = np.ascontiguousarray(shift, dtype=np.uint64)
+    p = _Params(dim, leaf_size, shift_seed & 0xFFFFFFFFFFFFFFFF, _hptr(sh), _hptr(lo), _hptr(hi))
+    return p, dim, n, off, ls, (lo, hi, sh)
+
+
+def zd_forest_build(xyz, offsets, leaf_size=16, leaf_sizes=None, box=None, shift_seed=0,
+                    shift=None, stream=None):
+    p, dim, n, off, ls, keep = _forest_args(xyz, offsets, leaf_size, leaf_sizes, box,
+                                            shift_seed, shift)
+    out = C.c_void_p()
+    _check(lib().zd_forest_build(C.byref(p), _dptr(xyz), n, _hptr(off), len(off) - 1, _hptr(ls),
+                                 _stream(stream), C.byref(out)), "zd_forest_build")
+    return out
+
+
+def zd_forest_knn(forest, k, out_ids, out_d2, stream=None):
+    _check(lib().zd_forest_knn(forest, k, _dptr(out_ids), _dptr(out_d2), _stream(stream)),
+           "zd_forest_knn")
+
+
+def zd_forest_plan(xyz, offsets, k, out_ids, out_d2, leaf_size=16, leaf_sizes=None, box=None,
+                   shift_seed=0, shift=None, stream=None):
+    p, dim, n, off, ls, keep = _forest_args(xyz, offsets, leaf_size, leaf_sizes, box,
+                                            shift_seed, shift)
+    out = C.c_void_p()
+    _check(lib().zd_forest_plan(C.byref(p), _dptr(xyz), n, _hptr(off), len(off) - 1, _hptr(ls),
+                                k, _dptr(out_ids), _dptr(out_d2), _stream(stream), C.byref(out)),
+           "zd_forest_plan")
+    return out
+
+
+def zd_forest_run(forest, stream=None):
+    _check(lib().zd_forest_run(forest, _stream(stream)), "zd_forest_run")
+
+
+def zd_forest_free(forest):
+    if forest:
+        _check(lib().zd_forest_free(forest), "zd_forest_free")
+
+
+class ZdForest:
+    """Many independent clouds in one device structure (cloud c = points
+    offsets[c]..offsets[c+1] of the SoA tensor xyz)."""
+
+    def __init__(self, xyz, offsets, leaf_size=16, leaf_sizes=None, box=None, shift_seed=0,
+                 shift=None, stream=None):
+        self.n = xyz.shape[1]
+        self._xyz = xyz
+        self._h = zd_forest_build(xyz, offsets, leaf_size, leaf_sizes, box, shift_seed, shift,
+                                  stream)
+
+    def knn(self, k, stream=None):
+        ids = torch.empty((self.n, k), dtype=torch.int32, device="cuda")
+        d2 = torch.empty((self.n, k), dtype=torch.float64, device="cuda")
+        zd_forest_knn(self._h, k, ids, d2, stream)
+        return ids, d2
+
+    def close(self):
+        if getattr(self, "_h", None):
+            zd_forest_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ZdForestPlan:
+    """Build + all-points query of a forest captured as one HIP graph; run()
+    replays it on the current contents of xyz, filling self.ids / self.d2."""
+
+    def __init__(self, xyz, offsets, k, leaf_size=16, leaf_sizes=None, box=None, shift_seed=0,
+                 shift=None, stream=None):
+        n = xyz.shape[1]
+        self._xyz = xyz
+        self.ids = torch.empty((n, k), dtype=torch.int32, device="cuda")
+        self.d2 = torch.empty((n, k), dtype=torch.float64, device="cuda")
+        self._h = zd_forest_plan(xyz, offsets, k, self.ids, self.d2, leaf_size, leaf_sizes, box,
+                                 shift_seed, shift, stream)
+
+    def run(self, stream=None):
+        zd_forest_run(self._h, stream)
+        return self.ids, self.d2
+
+    def close(self):
+        if getattr(self, "_h", None):
+            zd_forest_free(self._h)
             self._h = None
 
     def __del__(self):

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <vector>
 
 using namespace zd;
@@ -133,13 +134,17 @@ hipError_t bind_stream(zd_tree t, hipStream_t s) {
 }
 
 // Relink the tree over the points of t->st (keys sorted, coordinates and
-// slot map in place).
-hipError_t relink(zd_tree t) {
+// slot map in place).  A forest passes the cloud of every position and the
+// leaf size of every cloud.
+hipError_t relink(zd_tree t, const int32_t *seg = nullptr, const int32_t *seg_leaf = nullptr) {
   hipStream_t s = t->stream;
   int32_t *flag = nullptr;
   hipError_t e = dev_alloc_n(&flag, t->st.n, s);
   if (e != hipSuccess) return e;
-  e = build_tree_links(t->dim, t->L, t->st.n, t->buffers(flag), s);
+  BuildBuffers b = t->buffers(flag);
+  b.seg = seg;
+  b.seg_leaf = seg_leaf;
+  e = build_tree_links(t->dim, t->L, t->st.n, b, s);
   dev_release(flag, s);
   return e;
 }
@@ -538,6 +543,263 @@ zd_status zd_knn_backward(int32_t dim, const double *xyz, int64_t stride, int64_
   if (rows > 0 && (!ids || !grad_d2)) return ZD_EINVAL;
   return to_status(
       knn_backward(dim, xyz, stride, rows, k, ids, grad_d2, grad_xyz, (hipStream_t)stream));
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched forest
+// ---------------------------------------------------------------------------
+
+struct zd_forest_s {
+  zd_tree t = nullptr;          // all clouds in one tree whose top separates them
+  int32_t C = 0;
+  const double *xyz = nullptr;  // the caller's points (read by every build)
+  bool have_box = false;
+  double box_lo[3] = {0, 0, 0}, box_hi[3] = {0, 0, 0};
+  int64_t *offsets = nullptr;   // device [C+1]
+  int32_t *seg = nullptr;       // device [n]: cloud of each position
+  double *seg_lo = nullptr;     // device [C][3]
+  double *seg_S = nullptr;      // device [C][3]
+  int32_t *seg_leaf = nullptr;  // device [C] or null (one leaf size)
+  int4 *tiles = nullptr;        // sort tiles, none spanning two clouds
+  int ntiles = 0;
+  int2 *groups = nullptr;       // query groups, none spanning two clouds
+  int64_t ngroups = 0;
+  // captured build + query
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  Arena arena{nullptr, 0, 0};
+};
+
+namespace {
+
+void forest_destroy(zd_forest f) {
+  if (!f) return;
+  hipStream_t s = f->t ? f->t->stream : nullptr;
+  if (f->exec || f->arena.base) (void)hipStreamSynchronize(s);
+  if (f->exec) (void)hipGraphExecDestroy(f->exec);
+  if (f->graph) (void)hipGraphDestroy(f->graph);
+  if (f->arena.base) (void)hipFree(f->arena.base);
+  if (f->cap) (void)hipStreamDestroy(f->cap);
+  dev_release(f->offsets, s);
+  dev_release(f->seg, s);
+  dev_release(f->seg_lo, s);
+  dev_release(f->seg_S, s);
+  dev_release(f->seg_leaf, s);
+  dev_release(f->tiles, s);
+  dev_release(f->groups, s);
+  destroy(f->t);
+  delete f;
+}
+
+// Validate the cloud bounds, allocate everything a forest needs and upload
+// the tile and group tables (synchronous copies: plan-time only).
+zd_status forest_setup(const zd_params *p, const double *xyz, int64_t n, const int64_t *offsets,
+                       int32_t C, const int32_t *leaf_sizes, hipStream_t s, zd_forest *out) {
+  if (!p || !out || !offsets || C < 1) return ZD_EINVAL;
+  const int dim = p->dim;
+  if ((dim != 2 && dim != 3) || p->leaf_size < 1 || n < 0 || n > kMaxPoints) return ZD_EINVAL;
+  if (n > 0 && !xyz) return ZD_EINVAL;
+  if ((p->box_lo == nullptr) != (p->box_hi == nullptr)) return ZD_EINVAL;
+  if (offsets[0] != 0 || offsets[C] != n) return ZD_EINVAL;
+  for (int32_t c = 0; c < C; ++c)
+    if (offsets[c + 1] < offsets[c]) return ZD_EINVAL;
+  if (leaf_sizes)
+    for (int32_t c = 0; c < C; ++c)
+      if (leaf_sizes[c] < 1) return ZD_EINVAL;
+  const int B = 64 / dim;
+  if (p->box_lo) {
+    if (!finite3(p->box_lo, dim) || !finite3(p->box_hi, dim)) return ZD_EINVAL;
+    for (int c = 0; c < dim; ++c)
+      if (!(p->box_hi[c] > p->box_lo[c])) return ZD_EINVAL;
+  }
+  if (p->shift)
+    for (int c = 0; c < dim; ++c)
+      if (p->shift[c] >> (B - 1)) return ZD_EINVAL;
+
+  zd_forest f = new (std::nothrow) zd_forest_s();
+  zd_tree t = new (std::nothrow) zd_tree_s();
+  if (!f || !t) {
+    delete f;
+    delete t;
+    return ZD_ENOMEM;
+  }
+  f->t = t;
+  f->C = C;
+  f->xyz = xyz;
+  t->stream = s;
+  t->dim = dim;
+  t->L = p->leaf_size;
+  t->geo.dim = dim;
+  t->geo.B = B;
+  for (int c = 0; c < dim; ++c)
+    t->geo.shift[c] = p->shift ? p->shift[c]
+                               : (splitmix64(p->shift_seed, (uint64_t)c + 1) &
+                                  ((uint64_t(1) << (B - 1)) - 1));
+  if (p->box_lo) {
+    f->have_box = true;
+    for (int c = 0; c < dim; ++c) {
+      f->box_lo[c] = p->box_lo[c];
+      f->box_hi[c] = p->box_hi[c];
+    }
+  }
+  // tile and group tables
+  std::vector<int4> tiles;
+  std::vector<int2> groups;
+  for (int32_t c = 0; c < C; ++c) {
+    const int64_t a = offsets[c], b = offsets[c + 1], m = b - a;
+    const int nts = (int)((m + 4095) / 4096);
+    const int first = (int)tiles.size();
+    for (int lt = 0; lt < nts; ++lt) {
+      const int64_t st = a + (int64_t)lt * 4096;
+      tiles.push_back(make_int4((int)st, (int)std::min<int64_t>(4096, b - st), 256 * first + lt,
+                                nts));
+    }
+    for (int64_t g = a; g < b; g += 64)
+      groups.push_back(make_int2((int)g, (int)std::min<int64_t>(g + 63, b - 1)));
+  }
+  f->ntiles = (int)tiles.size();
+  f->ngroups = (int64_t)groups.size();
+  hipError_t e = dev_alloc_n(&t->meta, kMetaCount, s);
+  if (e == hipSuccess) e = dev_alloc_n(&t->root_box, 6, s);
+  if (e == hipSuccess) e = fill_i32(t->meta, 0, kMetaCount, s);
+  if (e == hipSuccess) e = grow_ids(t, n);
+  if (e == hipSuccess) e = store_alloc(t->st, n, dim, s);
+  if (e == hipSuccess) e = dev_alloc_n(&f->offsets, C + 1, s);
+  if (e == hipSuccess) e = dev_alloc_n(&f->seg, n, s);
+  if (e == hipSuccess) e = dev_alloc_n(&f->seg_lo, (int64_t)C * 3, s);
+  if (e == hipSuccess) e = dev_alloc_n(&f->seg_S, (int64_t)C * 3, s);
+  if (e == hipSuccess && leaf_sizes) e = dev_alloc_n(&f->seg_leaf, C, s);
+  if (e == hipSuccess) e = dev_alloc_n(&f->tiles, f->ntiles, s);
+  if (e == hipSuccess) e = dev_alloc_n(&f->groups, f->ngroups, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess)
+    e = hipMemcpy(f->offsets, offsets, sizeof(int64_t) * (C + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess && leaf_sizes)
+    e = hipMemcpy(f->seg_leaf, leaf_sizes, sizeof(int32_t) * C, hipMemcpyHostToDevice);
+  if (e == hipSuccess && f->ntiles)
+    e = hipMemcpy(f->tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && f->ngroups)
+    e = hipMemcpy(f->groups, groups.data(), sizeof(int2) * groups.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    forest_destroy(f);
+    return to_status(e);
+  }
+  t->cap = n;
+  *out = f;
+  return ZD_OK;
+}
+
+// Build all clouds (stream-ordered, no host synchronisation, no allocator
+// call when an arena is active).
+hipError_t forest_build_pass(zd_forest f, hipStream_t s) {
+  zd_tree t = f->t;
+  const int64_t n = t->st.n;
+  t->stream = s;
+  hipError_t e = forest_geometry(t->dim, f->xyz, n, f->offsets, f->C, t->geo.B,
+                                 f->have_box ? f->box_lo : nullptr,
+                                 f->have_box ? f->box_hi : nullptr, f->seg, f->seg_lo, f->seg_S,
+                                 s);
+  if (e == hipSuccess)
+    e = encode_keys_seg(t->geo, f->xyz, n, f->seg, f->seg_lo, f->seg_S, t->st.key, t->st.id, s);
+  uint64_t *ktmp = nullptr;
+  int32_t *itmp = nullptr;
+  if (e == hipSuccess && n > 1) e = dev_alloc_n(&ktmp, n, s);
+  if (e == hipSuccess && n > 1) e = dev_alloc_n(&itmp, n, s);
+  if (e == hipSuccess)
+    e = radix_sort_pairs(t->st.key, t->st.id, ktmp, itmp, n, t->dim * t->geo.B, s, f->tiles,
+                         f->ntiles);
+  dev_release(ktmp, s);
+  dev_release(itmp, s);
+  if (e == hipSuccess)
+    e = gather_points(t->dim, f->xyz, n, t->st.id, n, t->st.X, t->st.Y, t->st.Z, t->slot_of, s);
+  if (e == hipSuccess) e = relink(t, f->seg, f->seg_leaf);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+zd_status zd_forest_build(const zd_params *params, const double *xyz, int64_t n,
+                          const int64_t *offsets, int32_t n_clouds, const int32_t *leaf_sizes,
+                          void *stream, zd_forest *out) {
+  zd_forest f = nullptr;
+  zd_status st = forest_setup(params, xyz, n, offsets, n_clouds, leaf_sizes, (hipStream_t)stream,
+                              &f);
+  if (st != ZD_OK) return st;
+  hipError_t e = forest_build_pass(f, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    forest_destroy(f);
+    return to_status(e);
+  }
+  *out = f;
+  return ZD_OK;
+}
+
+zd_status zd_forest_knn(zd_forest f, int32_t k, int32_t *out_ids, double *out_d2, void *stream) {
+  if (!f || k < 1) return ZD_EINVAL;
+  if (k > ZD_KMAX) return ZD_EKMAX;
+  if (f->t->broken) return ZD_EDEVICE;
+  if (f->t->st.n > 0 && (!out_ids || !out_d2)) return ZD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = bind_stream(f->t, s);
+  if (e == hipSuccess)
+    e = knn_all_points(f->t->dim, f->t->view(), k, out_ids, out_d2, s, f->groups, f->ngroups);
+  return to_status(e);
+}
+
+zd_status zd_forest_plan(const zd_params *params, const double *xyz, int64_t n,
+                         const int64_t *offsets, int32_t n_clouds, const int32_t *leaf_sizes,
+                         int32_t k, int32_t *out_ids, double *out_d2, void *stream,
+                         zd_forest *out) {
+  if (k < 1) return ZD_EINVAL;
+  if (k > ZD_KMAX) return ZD_EKMAX;
+  if (n > 0 && (!out_ids || !out_d2)) return ZD_EINVAL;
+  zd_forest f = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  zd_status st = forest_setup(params, xyz, n, offsets, n_clouds, leaf_sizes, s, &f);
+  if (st != ZD_OK) return st;
+  // scratch for one build + query: sort buffers, digit counts, scan sums,
+  // split flags, with room to spare
+  f->arena.size = (size_t)n * 24 + ((size_t)64 << 20);
+  hipError_t e = hipMalloc(&f->arena.base, f->arena.size);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&f->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipStreamBeginCapture(f->cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    arena_activate(&f->arena);
+    hipError_t e1 = forest_build_pass(f, f->cap);
+    if (e1 == hipSuccess)
+      e1 = knn_all_points(f->t->dim, f->t->view(), k, out_ids, out_d2, f->cap, f->groups,
+                          f->ngroups);
+    arena_activate(nullptr);
+    hipError_t e2 = hipStreamEndCapture(f->cap, &f->graph);
+    e = e1 != hipSuccess ? e1 : e2;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&f->exec, f->graph, nullptr, nullptr, 0);
+  f->t->stream = s;
+  if (e != hipSuccess) {
+    forest_destroy(f);
+    return to_status(e);
+  }
+  *out = f;
+  return ZD_OK;
+}
+
+zd_status zd_forest_run(zd_forest f, void *stream) {
+  if (!f || !f->exec) return ZD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = bind_stream(f->t, s);
+  if (e == hipSuccess) e = hipGraphLaunch(f->exec, s);
+  return to_status(e);
+}
+
+zd_status zd_forest_free(zd_forest f) {
+  forest_destroy(f);
+  return ZD_OK;
 }
 
 }  // extern "C"

@@ -56,6 +56,110 @@ hipError_t encode_keys(const Geometry &g, const double *xyz, int64_t stride, int
   return hipGetLastError();
 }
 
+// ------------------------------------------------------- forest: geometry --
+
+// One block per cloud: mark the cloud's positions, reduce its bounding box,
+// and derive the cloud's own key geometry the way zd_build does for a single
+// tree (lo = minimum, common side = largest extent or 1, S = 2^(B-1)/side;
+// with a declared box, that box for every cloud).
+template <int D>
+__global__ void __launch_bounds__(256) k_seg_geometry(const double *__restrict__ xyz, int64_t n,
+                                                      const int64_t *__restrict__ offsets,
+                                                      int B, int have_box, Box3 box,
+                                                      int32_t *__restrict__ seg,
+                                                      double *__restrict__ seg_lo,
+                                                      double *__restrict__ seg_S) {
+  __shared__ double red[6][256];
+  const int c = blockIdx.x;
+  const int64_t a = offsets[c], b = offsets[c + 1];
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) {
+    seg[i] = c;
+    for (int d = 0; d < D; ++d) {
+      const double v = xyz[d * n + i];
+      lo[d] = fmin(lo[d], v);
+      hi[d] = fmax(hi[d], v);
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    red[d][threadIdx.x] = lo[d];
+    red[3 + d][threadIdx.x] = hi[d];
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int d = 0; d < 3; ++d) {
+        red[d][threadIdx.x] = fmin(red[d][threadIdx.x], red[d][threadIdx.x + w]);
+        red[3 + d][threadIdx.x] = fmax(red[3 + d][threadIdx.x], red[3 + d][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double cells = ldexp(1.0, B - 1);
+    if (have_box) {
+      for (int d = 0; d < D; ++d) {
+        seg_lo[c * 3 + d] = box.lo[d];
+        seg_S[c * 3 + d] = cells / (box.hi[d] - box.lo[d]);
+      }
+    } else {
+      double side = 0.0;
+      for (int d = 0; d < D; ++d)
+        if (red[3 + d][0] - red[d][0] > side) side = red[3 + d][0] - red[d][0];
+      if (!(side > 0.0)) side = 1.0;
+      for (int d = 0; d < D; ++d) {
+        seg_lo[c * 3 + d] = b > a ? red[d][0] : 0.0;
+        seg_S[c * 3 + d] = cells / side;
+      }
+    }
+  }
+}
+
+template <int D>
+__global__ void k_encode_seg(const double *__restrict__ xyz, int64_t n,
+                             const int32_t *__restrict__ seg, const double *__restrict__ seg_lo,
+                             const double *__restrict__ seg_S, Geometry g,
+                             uint64_t *__restrict__ key, int32_t *__restrict__ id) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = seg[i];
+  Geometry gc = g;
+  for (int d = 0; d < D; ++d) {
+    gc.lo[d] = seg_lo[c * 3 + d];
+    gc.S[d] = seg_S[c * 3 + d];
+  }
+  key[i] = morton_key<D>(gc, xyz[i], xyz[n + i], D == 3 ? xyz[2 * n + i] : 0.0);
+  id[i] = (int32_t)i;
+}
+
+hipError_t forest_geometry(int dim, const double *xyz, int64_t n, const int64_t *offsets, int C,
+                           int B, const double *box_lo, const double *box_hi, int32_t *seg,
+                           double *seg_lo, double *seg_S, hipStream_t s) {
+  if (C <= 0) return hipSuccess;
+  Box3 box{};
+  const int have = box_lo != nullptr;
+  for (int d = 0; d < dim && have; ++d) {
+    box.lo[d] = box_lo[d];
+    box.hi[d] = box_hi[d];
+  }
+  if (dim == 3)
+    k_seg_geometry<3><<<C, 256, 0, s>>>(xyz, n, offsets, B, have, box, seg, seg_lo, seg_S);
+  else
+    k_seg_geometry<2><<<C, 256, 0, s>>>(xyz, n, offsets, B, have, box, seg, seg_lo, seg_S);
+  return hipGetLastError();
+}
+
+hipError_t encode_keys_seg(const Geometry &g, const double *xyz, int64_t n, const int32_t *seg,
+                           const double *seg_lo, const double *seg_S, uint64_t *key, int32_t *id,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  unsigned grid = (unsigned)((n + 255) / 256);
+  if (g.dim == 3)
+    k_encode_seg<3><<<grid, 256, 0, s>>>(xyz, n, seg, seg_lo, seg_S, g, key, id);
+  else
+    k_encode_seg<2><<<grid, 256, 0, s>>>(xyz, n, seg, seg_lo, seg_S, g, key, id);
+  return hipGetLastError();
+}
+
 // ----------------------------------------------------------------- gather --
 
 template <int D>
@@ -91,26 +195,44 @@ __device__ __forceinline__ bool same_prefix(uint64_t a, uint64_t b, int bit) {
   return bit >= 63 ? true : ((a ^ b) >> (bit + 1)) == 0;
 }
 
-__global__ void k_split_flags(const uint64_t *__restrict__ key, int64_t n, int L,
+// Split bit between sorted positions i and i+1.  In a forest the order is by
+// (cloud, key): a change of cloud splits above every key bit, at 64 + the
+// highest differing bit of the cloud numbers, so the top of the tree
+// separates the clouds and each cloud's subtree is its own zd-tree.
+__device__ __forceinline__ int pos_split_bit(const uint64_t *key, const int32_t *seg, int64_t i) {
+  if (seg) {
+    const uint32_t a = (uint32_t)seg[i], b = (uint32_t)seg[i + 1];
+    if (a != b) return 64 + 31 - __clz((int)(a ^ b));
+  }
+  return split_bit(key[i], key[i + 1]);
+}
+
+__global__ void k_split_flags(const uint64_t *__restrict__ key, const int32_t *__restrict__ seg,
+                              int64_t n, int L, const int32_t *__restrict__ seg_leaf,
                               int32_t *__restrict__ flag) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n - 1) return;
-  const uint64_t ki = key[i];
-  const int b = split_bit(ki, key[i + 1]);
+  const int b = pos_split_bit(key, seg, i);
   int32_t f = 0;
-  if (b >= 0) {
+  if (b >= 64) {
+    f = 1;  // cloud boundaries are always internal: no leaf mixes clouds
+  } else if (b >= 0) {
     // points i and i+1 are on the two sides; extend each side while the keys
-    // keep the node's prefix, stopping as soon as more than L points are seen
+    // keep the node's prefix (and cloud), stopping once more than L points
+    // are seen
+    const uint64_t ki = key[i];
+    const int32_t si = seg ? seg[i] : 0;
+    const int Li = seg_leaf ? seg_leaf[si] : L;
     int64_t left = 1, right = 1;
-    for (int64_t x = i - 1; x >= 0 && left + right <= L; --x) {
-      if (!same_prefix(key[x], ki, b)) break;
+    for (int64_t x = i - 1; x >= 0 && left + right <= Li; --x) {
+      if ((seg && seg[x] != si) || !same_prefix(key[x], ki, b)) break;
       ++left;
     }
-    for (int64_t x = i + 2; x < n && left + right <= L; ++x) {
-      if (!same_prefix(key[x], ki, b)) break;
+    for (int64_t x = i + 2; x < n && left + right <= Li; ++x) {
+      if ((seg && seg[x] != si) || !same_prefix(key[x], ki, b)) break;
       ++right;
     }
-    f = (left + right > L) ? 1 : 0;
+    f = (left + right > Li) ? 1 : 0;
   }
   flag[i] = f;
 }
@@ -118,12 +240,13 @@ __global__ void k_split_flags(const uint64_t *__restrict__ key, int64_t n, int L
 // ---------------------------------------------------------------- compact --
 
 __global__ void k_compact(const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
-                          const uint64_t *__restrict__ key, int64_t n, INode *__restrict__ inode) {
+                          const uint64_t *__restrict__ key, const int32_t *__restrict__ seg,
+                          int64_t n, INode *__restrict__ inode) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n - 1 || !flag[i]) return;
   INode &N = inode[pos[i]];
   N.split = (int32_t)i;
-  N.bit = split_bit(key[i], key[i + 1]);
+  N.bit = pos_split_bit(key, seg, i);
   N.visits = 0;
   N.parent = -1;
 }
@@ -226,13 +349,13 @@ hipError_t build_tree_links(int dim, int leaf_size, int64_t n, const BuildBuffer
   }
   const unsigned grid_n = (unsigned)((n + 255) / 256);
   if (n > 1) {
-    k_split_flags<<<grid_n, 256, 0, s>>>(b.key, n, leaf_size, b.flag);
+    k_split_flags<<<grid_n, 256, 0, s>>>(b.key, b.seg, n, leaf_size, b.seg_leaf, b.flag);
     e = hipGetLastError();
     // exclusive positions overwrite leaf_of (free until the leaf pass)
     if (e == hipSuccess)
       e = exclusive_scan_i32(b.flag, b.leaf_of, n - 1, b.meta + kMetaInternal, s);
     if (e == hipSuccess) {
-      k_compact<<<grid_n, 256, 0, s>>>(b.flag, b.leaf_of, b.key, n, b.inode);
+      k_compact<<<grid_n, 256, 0, s>>>(b.flag, b.leaf_of, b.key, b.seg, n, b.inode);
       e = hipGetLastError();
     }
   } else {

@@ -181,9 +181,18 @@ __device__ __forceinline__ bool cand_lt(double d, int32_t i, double e, int32_t j
 // host-side internals (implemented across the .hip files)
 // ---------------------------------------------------------------------------
 
-// device allocation ordered on a stream (pool-backed)
+// device allocation ordered on a stream (pool-backed).  While an arena is
+// active on the calling thread (graph capture), allocations are carved from
+// it instead and releases are no-ops, so a captured graph calls no
+// allocator.
 hipError_t dev_alloc(void **p, size_t bytes, hipStream_t s);
 void dev_release(void *p, hipStream_t s);
+struct Arena {
+  char *base;
+  size_t size;
+  size_t used;
+};
+void arena_activate(Arena *a);  // nullptr deactivates
 
 template <typename T>
 hipError_t dev_alloc_n(T **p, int64_t n, hipStream_t s) {
@@ -202,8 +211,11 @@ hipError_t exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_
 
 // Stable LSD radix sort of (key, value) pairs by key bits [0, key_bits).
 // Sorted pairs end in (key, val); key_tmp/val_tmp are scratch of n entries.
+// With `tiles` (device, ntiles entries of {start, count, count base, tiles
+// in segment}) each segment of the array is sorted on its own.
 hipError_t radix_sort_pairs(uint64_t *key, int32_t *val, uint64_t *key_tmp, int32_t *val_tmp,
-                            int64_t n, int key_bits, hipStream_t s);
+                            int64_t n, int key_bits, hipStream_t s, const int4 *tiles = nullptr,
+                            int ntiles = 0);
 
 // Build kernels.  n points sorted by key in (key, id); the tree arrays have
 // room for n leaves and n internal nodes.
@@ -218,18 +230,30 @@ struct BuildBuffers {
   int32_t *meta;
   double *root_box;  // [6]: lo[3], hi[3]
   int32_t *flag;     // scratch [n]
+  const int32_t *seg = nullptr;       // forest: cloud of each sorted position
+  const int32_t *seg_leaf = nullptr;  // forest: leaf size of each cloud
 };
 hipError_t encode_keys(const Geometry &g, const double *xyz, int64_t stride, int64_t n,
                        int32_t id_base, uint64_t *key, int32_t *id, hipStream_t s);
+// Forest: per-cloud key geometry (seg_lo/seg_S [C][3]) and the cloud of
+// every point (seg [n]); offsets is a device copy of the cloud bounds.
+hipError_t forest_geometry(int dim, const double *xyz, int64_t n, const int64_t *offsets, int C,
+                           int B, const double *box_lo, const double *box_hi, int32_t *seg,
+                           double *seg_lo, double *seg_S, hipStream_t s);
+hipError_t encode_keys_seg(const Geometry &g, const double *xyz, int64_t n, const int32_t *seg,
+                           const double *seg_lo, const double *seg_S, uint64_t *key, int32_t *id,
+                           hipStream_t s);
 hipError_t gather_points(int dim, const double *xyz, int64_t stride, const int32_t *id,
                          int64_t n, double *X, double *Y, double *Z, int32_t *slot_of,
                          hipStream_t s);
 hipError_t build_tree_links(int dim, int leaf_size, int64_t n, const BuildBuffers &b,
                             hipStream_t s);
 
-// Queries
+// Queries.  groups == nullptr: wavefront w answers sorted positions
+// [64w, 64w + 64); otherwise wavefront w answers [groups[w].x, groups[w].y]
+// (a forest's groups never span two clouds).
 hipError_t knn_all_points(int dim, const TreeView &t, int k, int32_t *out_ids, double *out_d2,
-                          hipStream_t s);
+                          hipStream_t s, const int2 *groups = nullptr, int64_t ngroups = 0);
 hipError_t knn_external(int dim, const TreeView &t, const Geometry &g, const double *q,
                         int64_t m, int k, int32_t *out_ids, double *out_d2, hipStream_t s);
 hipError_t fill_dead_rows(const int32_t *slot_of, int64_t cap, int k, int32_t *out_ids,

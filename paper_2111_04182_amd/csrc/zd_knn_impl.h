@@ -211,6 +211,7 @@ struct WaveSearch {
       const int32_t p = link >> 1;
       const int side = link & 1;
       const INode *P = &t.inode[p];
+      if (uni(P->bit) >= 64) break;  // a forest's cloud boundary: never cross it
       const bool out = valid && !ball_inside<D>(px, py, pz, P->lo[side], P->hi[side], h.kth());
       if (__ballot(out) == 0) break;
       const int os = 1 - side;
@@ -227,13 +228,22 @@ struct WaveSearch {
 // All-points rows: wavefront w answers sorted positions [64w, 64w + 64).
 template <int D, int K>
 __global__ void __launch_bounds__(256) k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
-                                                 double *__restrict__ out_d2) {
+                                                 double *__restrict__ out_d2,
+                                                 const int2 *__restrict__ groups, int64_t ngroups) {
   __shared__ Cand stage_all[4][64];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int64_t g0 = ((int64_t)blockIdx.x * 4 + w) * 64;
-  if (g0 >= t.n) return;
-  const int64_t last = min(g0 + 63, t.n - 1);
+  const int64_t gw = (int64_t)blockIdx.x * 4 + w;
+  int64_t g0, last;
+  if (groups) {
+    if (gw >= ngroups) return;
+    g0 = uni(groups[gw].x);
+    last = uni(groups[gw].y);
+  } else {
+    g0 = gw * 64;
+    if (g0 >= t.n) return;
+    last = min(g0 + 63, t.n - 1);
+  }
   const int64_t i = min(g0 + lane, last);
   WaveSearch<D, K> s(t, stage_all[w]);
   s.valid = g0 + lane <= last;
@@ -330,9 +340,10 @@ __global__ void __launch_bounds__(256) k_knn_ext(TreeView t, const double *__res
 }
 
 template <int D, int K>
-hipError_t launch_knn_all(const TreeView &t, int k, int32_t *ids, double *d2, hipStream_t s) {
-  const int64_t waves = (t.n + 63) / 64;
-  k_knn_all<D, K><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(t, k, ids, d2);
+hipError_t launch_knn_all(const TreeView &t, int k, int32_t *ids, double *d2, hipStream_t s,
+                          const int2 *groups, int64_t ngroups) {
+  const int64_t waves = groups ? ngroups : (t.n + 63) / 64;
+  k_knn_all<D, K><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(t, k, ids, d2, groups, ngroups);
   return hipGetLastError();
 }
 

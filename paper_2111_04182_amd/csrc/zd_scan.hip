@@ -21,7 +21,18 @@ static void configure_pool(int dev) {
   }
 }
 
+static thread_local Arena *tl_arena = nullptr;
+
+void arena_activate(Arena *a) { tl_arena = a; }
+
 hipError_t dev_alloc(void **p, size_t bytes, hipStream_t s) {
+  if (tl_arena) {
+    const size_t off = (tl_arena->used + 255) & ~size_t(255);
+    if (off + bytes > tl_arena->size) return hipErrorOutOfMemory;
+    *p = tl_arena->base + off;
+    tl_arena->used = off + bytes;
+    return hipSuccess;
+  }
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -30,7 +41,10 @@ hipError_t dev_alloc(void **p, size_t bytes, hipStream_t s) {
 }
 
 void dev_release(void *p, hipStream_t s) {
-  if (p) (void)hipFreeAsync(p, s);
+  if (!p) return;
+  if (tl_arena && (char *)p >= tl_arena->base && (char *)p < tl_arena->base + tl_arena->size)
+    return;
+  (void)hipFreeAsync(p, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -24,26 +24,52 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) {
   return (uint32_t)(k >> shift) & (kRadix - 1);
 }
 
+// A tile is at most kSortTile consecutive keys inside one segment; its
+// digit counts live at cbase + digit * nts (nts = tiles of its segment), so
+// one exclusive scan over all counts in (segment, digit, tile) order gives
+// every (tile, digit) its output base.  With tiles == nullptr the whole
+// array is one segment cut into uniform tiles.
+struct TileInfo {
+  int64_t start, end, cbase, nts;
+};
+
+__device__ __forceinline__ TileInfo tile_info(const int4 *tiles, int64_t n, int ntiles) {
+  TileInfo ti;
+  if (tiles) {
+    const int4 d = tiles[blockIdx.x];
+    ti.start = d.x;
+    ti.end = (int64_t)d.x + d.y;
+    ti.cbase = d.z;
+    ti.nts = d.w;
+  } else {
+    ti.start = (int64_t)blockIdx.x * kSortTile;
+    ti.end = min(ti.start + kSortTile, n);
+    ti.cbase = blockIdx.x;
+    ti.nts = ntiles;
+  }
+  return ti;
+}
+
 __global__ void __launch_bounds__(kSortThreads) k_radix_count(const uint64_t *key, int64_t n,
                                                               int shift, int32_t *counts,
-                                                              int ntiles) {
+                                                              int ntiles, const int4 *tiles) {
   __shared__ int32_t hist[kRadix];
   hist[threadIdx.x] = 0;
   __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const TileInfo ti = tile_info(tiles, n, ntiles);
 #pragma unroll 4
   for (int j = 0; j < kSortItems; ++j) {
-    int64_t i = base + (int64_t)j * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&hist[digit_of(key[i], shift)], 1);
+    int64_t i = ti.start + (int64_t)j * kSortThreads + threadIdx.x;
+    if (i < ti.end) atomicAdd(&hist[digit_of(key[i], shift)], 1);
   }
   __syncthreads();
-  counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = hist[threadIdx.x];
+  counts[ti.cbase + (int64_t)threadIdx.x * ti.nts] = hist[threadIdx.x];
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const uint64_t *__restrict__ key_in, const int32_t *__restrict__ val_in,
     uint64_t *__restrict__ key_out, int32_t *__restrict__ val_out, int64_t n, int shift,
-    const int32_t *__restrict__ offsets, int ntiles) {
+    const int32_t *__restrict__ offsets, int ntiles, const int4 *tiles) {
   __shared__ int32_t wcount[kSortWaves][kRadix];
   __shared__ int32_t gbase[kRadix];
   const int lane = threadIdx.x & 63;
@@ -52,7 +78,8 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
   for (int i = 0; i < kSortWaves; ++i) wcount[i][threadIdx.x] = 0;
   __syncthreads();
 
-  const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)w * kWaveSpan;
+  const TileInfo ti = tile_info(tiles, n, ntiles);
+  const int64_t base = ti.start + (int64_t)w * kWaveSpan;
   const uint64_t lt_mask = lane ? (~0ULL >> (64 - lane)) : 0ULL;
   uint64_t k[kSortItems];
   int32_t v[kSortItems];
@@ -60,7 +87,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     int64_t i = base + r * 64 + lane;
-    bool valid = i < n;
+    bool valid = i < ti.end;
     k[r] = valid ? key_in[i] : 0;
     v[r] = valid ? val_in[i] : 0;
     uint32_t d = digit_of(k[r], shift);
@@ -87,13 +114,13 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
       wcount[i][d] = run;
       run += t;
     }
-    gbase[d] = offsets[(int64_t)d * ntiles + blockIdx.x];
+    gbase[d] = offsets[ti.cbase + (int64_t)d * ti.nts];
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     int64_t i = base + r * 64 + lane;
-    if (i < n) {
+    if (i < ti.end) {
       uint32_t d = digit_of(k[r], shift);
       int64_t pos = (int64_t)gbase[d] + wcount[w][d] + rank[r];
       key_out[pos] = k[r];
@@ -103,9 +130,10 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
 }
 
 hipError_t radix_sort_pairs(uint64_t *key, int32_t *val, uint64_t *key_tmp, int32_t *val_tmp,
-                            int64_t n, int key_bits, hipStream_t s) {
+                            int64_t n, int key_bits, hipStream_t s, const int4 *tiles,
+                            int ntiles_seg) {
   if (n <= 1) return hipSuccess;
-  const int ntiles = (int)((n + kSortTile - 1) / kSortTile);
+  const int ntiles = tiles ? ntiles_seg : (int)((n + kSortTile - 1) / kSortTile);
   const int64_t ncounts = (int64_t)kRadix * ntiles;
   int32_t *counts = nullptr;
   hipError_t e = dev_alloc_n(&counts, ncounts, s);
@@ -114,11 +142,12 @@ hipError_t radix_sort_pairs(uint64_t *key, int32_t *val, uint64_t *key_tmp, int3
   int32_t *va = val, *vb = val_tmp;
   int passes = 0;
   for (int shift = 0; shift < key_bits && e == hipSuccess; shift += kRadixBits) {
-    k_radix_count<<<ntiles, kSortThreads, 0, s>>>(ka, n, shift, counts, ntiles);
+    k_radix_count<<<ntiles, kSortThreads, 0, s>>>(ka, n, shift, counts, ntiles, tiles);
     e = hipGetLastError();
     if (e == hipSuccess) e = exclusive_scan_i32(counts, counts, ncounts, nullptr, s);
     if (e == hipSuccess) {
-      k_radix_scatter<<<ntiles, kSortThreads, 0, s>>>(ka, va, kb, vb, n, shift, counts, ntiles);
+      k_radix_scatter<<<ntiles, kSortThreads, 0, s>>>(ka, va, kb, vb, n, shift, counts, ntiles,
+                                                      tiles);
       e = hipGetLastError();
     }
     uint64_t *tk = ka; ka = kb; kb = tk;
