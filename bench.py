@@ -15,7 +15,18 @@ oracle's work counters on this workload) with the chip's FP64 vector issue
 rate.  The CPU oracle is timed on a bounded sample for the cpu_baseline
 entry, and sampled GPU rows are checked against it after the timed region.
 
-Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu]
+Other workloads (one JSON line each, not the headline):
+  --workload spheres   10M points on 64 noisy spheres + 1% background:
+                       build, all-points k=10 and k=50.
+  --workload forest    4096 Gaussian-mixture clouds (1,000-65,536 points):
+                       autotuned leaf sizes, build + all-points k=16 as one
+                       replayed HIP graph, against one build + query call
+                       pair per cloud on the same GPU.
+  --workload grad      1M uniform points, k=8: forward rows, backward kernel,
+                       10 rounds of 1% insert + 1% delete; central finite
+                       differences checked on 1,000 sampled coordinates.
+
+Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu] [--workload W]
 """
 from __future__ import annotations
 
@@ -87,6 +98,8 @@ def main():
     ap.add_argument("--leaf", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=500_000)
+    ap.add_argument("--workload", default="uniform3d",
+                    choices=["uniform3d", "spheres", "forest", "grad"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -100,6 +113,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload != "uniform3d":
+        {"spheres": bench_spheres, "forest": bench_forest, "grad": bench_grad}[args.workload](args)
+        return
     n, m, k, L = args.n, args.m, args.k, args.leaf
     log(f"bench: generating inputs n={n} m={m}")
     P = W.uniform(n, 3, 0)
@@ -196,6 +212,176 @@ def main():
         result["verified"] = bool(np.array_equal(gi, wi) and np.array_equal(gd, wd))
     tree.close()
     print(json.dumps(result), flush=True)
+
+
+def _events(fn, reps):
+    import torch
+    best = float("inf")
+    out = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best, out
+
+
+def bench_spheres(args):
+    import torch
+    import paper_2111_04182_amd as zd
+    import workloads as W
+    log("bench spheres: generating 10M sphere-surface points")
+    P = W.cfg3_spheres()
+    xyz = zd.soa(torch.from_numpy(P))
+    n = P.shape[0]
+    res = {}
+    trees = []
+
+    def build():
+        t = zd.ZdTree(xyz, args.leaf, shift_seed=0)
+        trees.append(t)
+        return t
+
+    ms_build, tree = _events(build, max(2, args.steps))
+    res["build_ms"] = ms_build
+    for k in (10, 50):
+        ms, _ = _events(lambda: tree.knn(k), max(2, args.steps))
+        res[f"query_k{k}_ms"] = ms
+    total = res["build_ms"] + res["query_k10_ms"] + res["query_k50_ms"]
+    print(json.dumps({
+        "metric": "all-points kNN queries/s, 3D clustered spheres 10M (k=10 and k=50)",
+        "value": 2 * n / (total / 1e3), "unit": "queries/s", "n_gpus": 1, "dtype": "f64",
+        "data": "synthetic", "config": {"workload": "64 noisy spheres + 1% background, n=10M, "
+                                                    "leaf 16: build, k=10, k=50", "n": n},
+        "build_mpts_s": n / res["build_ms"] / 1e3, "query_k10_qps": n / res["query_k10_ms"] * 1e3,
+        "query_k50_qps": n / res["query_k50_ms"] * 1e3, "phase_ms": res}), flush=True)
+
+
+def bench_forest(args):
+    import torch
+    import paper_2111_04182_amd as zd
+    import workloads as W
+    from paper_2111_04182_amd.autotune import tune_forest
+    k = 16
+    log("bench forest: generating 4096 clouds")
+    P, off = W.cfg4_forest()
+    N = P.shape[0]
+    xyz = zd.soa(torch.from_numpy(P))
+    log(f"bench forest: N={N}, autotuning leaf sizes")
+    ls, rep = tune_forest(xyz, off, k, reps=1, log=log)
+    plan = zd.ZdForestPlan(xyz, off, k, leaf_sizes=ls)
+    plan.run()
+    torch.cuda.synchronize()
+    ms_forest, _ = _events(plan.run, max(3, args.steps))
+    # the same work as one zd_build + zd_knn pair per cloud (boxes precomputed
+    # on the host so no call synchronises)
+    clouds = []
+    for c in range(len(off) - 1):
+        a, b = int(off[c]), int(off[c + 1])
+        sub = P[a:b]
+        lo = sub.min(axis=0)
+        side = float((sub.max(axis=0) - lo).max()) or 1.0
+        clouds.append((a, b, zd.soa(torch.from_numpy(sub)), (lo, lo + side), int(ls[c])))
+    ids_pc = torch.empty((N, k), dtype=torch.int32, device="cuda")
+    d2_pc = torch.empty((N, k), dtype=torch.float64, device="cuda")
+
+    def per_cloud():
+        for a, b, cx, box, L in clouds:
+            t = zd.ZdTree(cx, L, box=box)
+            zd.zd_knn(t.handle, None, b - a, k, ids_pc[a:b], d2_pc[a:b])
+            t.close()
+
+    per_cloud()
+    torch.cuda.synchronize()
+    ms_pc, _ = _events(per_cloud, 1)
+    # same rows (ids of the per-cloud calls are local to the cloud)
+    ok = True
+    for a, b, _, _, _ in clouds[::64]:
+        li = ids_pc[a:b]
+        gi = torch.where(li >= 0, li + a, li)
+        ok &= bool(torch.equal(gi, plan.ids[a:b]) and torch.equal(d2_pc[a:b], plan.d2[a:b]))
+    print(json.dumps({
+        "metric": "batched forest all-points kNN queries/s (4096 clouds, k=16)",
+        "value": N / (ms_forest / 1e3), "unit": "queries/s", "n_gpus": 1, "dtype": "f64",
+        "data": "synthetic", "config": {"workload": "4096 Gaussian-mixture clouds, sizes "
+                                                    "log-uniform 1000-65536, k=16", "N": N},
+        "forest_graph_ms": ms_forest, "per_cloud_calls_ms": ms_pc,
+        "speedup_vs_per_cloud": ms_pc / ms_forest, "rows_match_per_cloud": ok,
+        "leaf_size_by_bucket": rep.get("choice"), "autotune_best_ms": rep.get("best_ms")}),
+        flush=True)
+
+
+def bench_grad(args):
+    import torch
+    import paper_2111_04182_amd as zd
+    import workloads as W
+    k = 8
+    P, fd, inserts, delete_rngs, m = W.cfg5_uniform3d()
+    n0 = P.shape[0]
+    pts = P.copy()
+    live = np.ones(n0, dtype=bool)
+    tree = zd.ZdTree(zd.soa(torch.from_numpy(P)), 16, box=W.UNIT3)
+    times = {"forward": [], "backward": [], "insert": [], "delete": []}
+    worst = 0.0
+    checked = 0
+    for r in range(len(inserts)):
+        xyz = zd.soa(torch.from_numpy(pts)).requires_grad_(True)
+        live_t = torch.from_numpy(live).cuda()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        d2, ids = zd.knn_sq_dist(xyz, tree, k)
+        e[1].record()
+        d2[live_t].sum().backward()
+        e[2].record()
+        torch.cuda.synchronize()
+        times["forward"].append(e[0].elapsed_time(e[1]))
+        times["backward"].append(e[1].elapsed_time(e[2]))
+        # central finite differences of the local loss (the terms touching
+        # the perturbed point) on the sampled coordinates, untimed
+        g = xyz.grad.detach().cpu().numpy().T
+        nb = ids.cpu().numpy()
+        rows = np.arange(len(pts))
+        for i, c in fd[: 1000 if r == 0 else 100]:
+            if not live[i]:
+                continue
+            touch = (((rows == i)[:, None] | (nb == i)) & live[:, None]) & (nb >= 0)
+            rr, jj = np.nonzero(touch)
+
+            def local(Q):
+                diff = Q[rr] - Q[nb[rr, jj]]
+                return float(np.sum(diff * diff))
+
+            h = 1e-6
+            Pp, Pm = pts.copy(), pts.copy()
+            Pp[i, c] += h
+            Pm[i, c] -= h
+            fdv = (local(Pp) - local(Pm)) / (Pp[i, c] - Pm[i, c])
+            worst = max(worst, abs(fdv - g[i, c]) / max(1e-30, abs(g[i, c])))
+            checked += 1
+        # 1% insert, 1% delete
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        tree.insert(zd.soa(torch.from_numpy(inserts[r])))
+        e[1].record()
+        pts = np.concatenate([pts, inserts[r]])
+        live = np.concatenate([live, np.ones(m, dtype=bool)])
+        D = delete_rngs[r].choice(np.flatnonzero(live), m, replace=False).astype(np.int32)
+        tree.delete(torch.from_numpy(D).cuda())
+        e[2].record()
+        torch.cuda.synchronize()
+        times["insert"].append(e[0].elapsed_time(e[1]))
+        times["delete"].append(e[1].elapsed_time(e[2]))
+        live[D] = False
+    med = {kk: float(np.median(v)) for kk, v in times.items()}
+    print(json.dumps({
+        "metric": "differentiable k=8 squared-distance loss, 1M points, 10 update rounds",
+        "value": n0 / (med["forward"] + med["backward"]) * 1e3, "unit": "points/s (fwd+bwd)",
+        "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "3D uniform n=1M, k=8, 1% insert + 1% delete per round"},
+        "median_ms": med, "fd_checked": checked, "fd_max_rel_err": worst}), flush=True)
 
 
 if __name__ == "__main__":

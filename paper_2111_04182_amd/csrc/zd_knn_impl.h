@@ -87,6 +87,104 @@ struct Heap {
   }
 };
 
+// For larger k the candidate set is a binary max-heap of the k best (d2, id)
+// per lane, kept in LDS (slot-major: slot s of lane l at [s * 64 + l], so a
+// lane's bank never depends on the slot it touches).  Replacing the root and
+// sifting down costs O(log k) instead of the O(k) register shift, and the
+// register file stays small.  The root (the k-th entry) is mirrored in
+// registers for the entry test; the rows are produced by one heap sort.
+template <int K>
+struct LdsHeap {
+  double *hd;     // [K][64] this wavefront's distances
+  int32_t *hi;    // [K][64] this wavefront's ids
+  int k;
+  double root_d;
+  int32_t root_i;
+
+  __device__ __forceinline__ void bind(double *d, int32_t *i) {
+    hd = d;
+    hi = i;
+  }
+
+  __device__ __forceinline__ void init(int k_) {
+    const int lane = threadIdx.x & 63;
+    k = k_;
+    for (int s = 0; s < k; ++s) {
+      hd[s * 64 + lane] = INFINITY;
+      hi[s * 64 + lane] = INT_MAX;
+    }
+    root_d = INFINITY;
+    root_i = INT_MAX;
+  }
+
+  __device__ __forceinline__ double kth() const { return root_d; }
+
+  // sift `dd, q` down from slot i within the first `size` slots
+  __device__ __forceinline__ void sift(int i, int size, double dd, int32_t q) {
+    const int lane = threadIdx.x & 63;
+    while (true) {
+      int c = 2 * i + 1;
+      if (c >= size) break;
+      double cd = hd[c * 64 + lane];
+      int32_t ci = hi[c * 64 + lane];
+      if (c + 1 < size) {
+        const double c2d = hd[(c + 1) * 64 + lane];
+        const int32_t c2i = hi[(c + 1) * 64 + lane];
+        if (cand_lt(cd, ci, c2d, c2i)) {
+          c = c + 1;
+          cd = c2d;
+          ci = c2i;
+        }
+      }
+      if (!cand_lt(dd, q, cd, ci)) break;  // the larger child does not exceed the item
+      hd[i * 64 + lane] = cd;
+      hi[i * 64 + lane] = ci;
+      i = c;
+    }
+    hd[i * 64 + lane] = dd;
+    hi[i * 64 + lane] = q;
+  }
+
+  __device__ __forceinline__ void offer(double dd, int32_t q) {
+    if (!cand_lt(dd, q, root_d, root_i)) return;
+    const int lane = threadIdx.x & 63;
+    sift(0, k, dd, q);
+    root_d = hd[lane];
+    root_i = hi[lane];
+  }
+
+  // heap sort: extract the worst into the last output slot, and so on
+  __device__ __forceinline__ void write(int k_, int32_t *out_ids, double *out_d2) {
+    const int lane = threadIdx.x & 63;
+    for (int size = k; size > 0; --size) {
+      const double d = hd[lane];
+      const int32_t i = hi[lane];
+      out_ids[size - 1] = i == INT_MAX ? -1 : i;
+      out_d2[size - 1] = d;
+      if (size > 1) sift(0, size - 1, hd[(size - 1) * 64 + lane], hi[(size - 1) * 64 + lane]);
+    }
+  }
+};
+
+template <int K>
+struct HeapFor {
+  using type = Heap<K>;
+  static constexpr bool lds = false;
+};
+#define ZD_LDS_HEAP(KK)                  \
+  template <>                            \
+  struct HeapFor<KK> {                   \
+    using type = LdsHeap<KK>;            \
+    static constexpr bool lds = true;    \
+  };
+ZD_LDS_HEAP(20)
+ZD_LDS_HEAP(24)
+ZD_LDS_HEAP(32)
+ZD_LDS_HEAP(40)
+ZD_LDS_HEAP(50)
+ZD_LDS_HEAP(64)
+#undef ZD_LDS_HEAP
+
 // withinBox(C, p, -r) of Algorithm 3, squared: p in the box and every face
 // strictly farther than the k-th d2 (never true while N holds fewer than k,
 // because the k-th d2 is then +inf).
@@ -123,7 +221,7 @@ struct WaveSearch {
   int32_t skip_lo, skip_hi;      // sorted positions already scored
   int64_t budget;                // walk bound (never reached on a valid tree)
   uint64_t key_ref;              // Morton key of the group's middle query (child order)
-  Heap<K> h;
+  typename HeapFor<K>::type h;
   __device__ __forceinline__ WaveSearch(const TreeView &t_, Cand *stage_) : t(t_), stage(stage_) {}
 
   __device__ __forceinline__ bool wants(const double *lo, const double *hi) const {
@@ -226,14 +324,34 @@ struct WaveSearch {
 };
 
 // All-points rows: wavefront w answers sorted positions [64w, 64w + 64).
+// LDS per wavefront: the 64-entry candidate stage, plus the heap for large k
+template <int K>
+constexpr size_t wave_lds_bytes() {
+  return 64 * sizeof(Cand) + (HeapFor<K>::lds ? (size_t)K * 64 * (sizeof(double) + sizeof(int32_t)) : 0);
+}
+template <int K>
+constexpr int waves_per_block() {
+  return HeapFor<K>::lds ? 1 : 4;
+}
+
+template <int D, int K>
+__device__ __forceinline__ void bind_lds(WaveSearch<D, K> &s, char *smem, int w) {
+  char *base = smem + (size_t)w * wave_lds_bytes<K>();
+  s.stage = reinterpret_cast<Cand *>(base);
+  if constexpr (HeapFor<K>::lds) {
+    double *hd = reinterpret_cast<double *>(base + 64 * sizeof(Cand));
+    s.h.bind(hd, reinterpret_cast<int32_t *>(hd + (size_t)K * 64));
+  }
+}
+
 template <int D, int K>
 __global__ void __launch_bounds__(256) k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
                                                  double *__restrict__ out_d2,
                                                  const int2 *__restrict__ groups, int64_t ngroups) {
-  __shared__ Cand stage_all[4][64];
+  extern __shared__ __align__(16) char smem[];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int64_t gw = (int64_t)blockIdx.x * 4 + w;
+  const int64_t gw = (int64_t)blockIdx.x * waves_per_block<K>() + w;
   int64_t g0, last;
   if (groups) {
     if (gw >= ngroups) return;
@@ -245,7 +363,8 @@ __global__ void __launch_bounds__(256) k_knn_all(TreeView t, int k, int32_t *__r
     last = min(g0 + 63, t.n - 1);
   }
   const int64_t i = min(g0 + lane, last);
-  WaveSearch<D, K> s(t, stage_all[w]);
+  WaveSearch<D, K> s(t, nullptr);
+  bind_lds(s, smem, w);
   s.valid = g0 + lane <= last;
   s.px = t.X[i];
   s.py = t.Y[i];
@@ -300,15 +419,16 @@ __global__ void __launch_bounds__(256) k_knn_ext(TreeView t, const double *__res
                                                  const int32_t *__restrict__ order, int64_t m,
                                                  int k, int32_t *__restrict__ out_ids,
                                                  double *__restrict__ out_d2) {
-  __shared__ Cand stage_all[4][64];
+  extern __shared__ __align__(16) char smem[];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int64_t g0 = ((int64_t)blockIdx.x * 4 + w) * 64;
+  const int64_t g0 = ((int64_t)blockIdx.x * waves_per_block<K>() + w) * 64;
   if (g0 >= m) return;
   const int64_t last = min(g0 + 63, m - 1);
   const int64_t i = min(g0 + lane, last);
   const int32_t r = order[i];
-  WaveSearch<D, K> s(t, stage_all[w]);
+  WaveSearch<D, K> s(t, nullptr);
+  bind_lds(s, smem, w);
   s.valid = g0 + lane <= last;
   s.px = q[r];
   s.py = q[m + r];
@@ -343,7 +463,9 @@ template <int D, int K>
 hipError_t launch_knn_all(const TreeView &t, int k, int32_t *ids, double *d2, hipStream_t s,
                           const int2 *groups, int64_t ngroups) {
   const int64_t waves = groups ? ngroups : (t.n + 63) / 64;
-  k_knn_all<D, K><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(t, k, ids, d2, groups, ngroups);
+  constexpr int wpb = waves_per_block<K>();
+  k_knn_all<D, K><<<(unsigned)((waves + wpb - 1) / wpb), 64 * wpb, wpb * wave_lds_bytes<K>(), s>>>(
+      t, k, ids, d2, groups, ngroups);
   return hipGetLastError();
 }
 
@@ -352,7 +474,9 @@ hipError_t launch_knn_ext(const TreeView &t, const double *q, const uint64_t *qk
                           const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
                           hipStream_t s) {
   const int64_t waves = (m + 63) / 64;
-  k_knn_ext<D, K><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(t, q, qkey, order, m, k, ids, d2);
+  constexpr int wpb = waves_per_block<K>();
+  k_knn_ext<D, K><<<(unsigned)((waves + wpb - 1) / wpb), 64 * wpb, wpb * wave_lds_bytes<K>(), s>>>(
+      t, q, qkey, order, m, k, ids, d2);
   return hipGetLastError();
 }
 

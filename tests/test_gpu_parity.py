@@ -282,3 +282,41 @@ def test_config2_full_size_sampled():
     dead = D[:100]
     assert (ids[torch.from_numpy(dead).cuda()].cpu().numpy() == -1).all()
     g.close()
+
+
+@pytest.mark.parametrize("k", [10, 50])
+def test_config3_spheres_scaled(k):
+    """Points on 64 noisy sphere surfaces plus uniform background (the
+    sphere-surface workload at 1/25 scale): full rows against brute force on a
+    sample, and against the oracle's own tree search on a larger sample."""
+    P = W.cfg3_spheres(n=400_000)
+    g = zd.ZdTree(dev(P), 16, shift_seed=2)
+    ids, d2 = g.knn(k)
+    rows = np.random.default_rng(k).choice(len(P), 4000, replace=False)
+    sel = torch.from_numpy(rows).cuda()
+    o = oracle.Tree(P, 16, seed=2)
+    assert_same_tree(g.export(), o.export(), 3, "config3 tree")
+    assert_same_rows((ids[sel], d2[sel]), o.knn_all(k, qids=rows), f"config3 k={k}")
+    few = rows[:40]
+    sel = torch.from_numpy(few).cuda()
+    assert_same_rows((ids[sel], d2[sel]), oracle.brute_knn(P, k, qids=few), f"config3 brute k={k}")
+    g.close()
+
+
+@pytest.mark.timeout(900)
+def test_config3_full_size_sampled():
+    """10M sphere-surface points, k = 10 and k = 50, sampled rows."""
+    P = W.cfg3_spheres()
+    print("config3: building", flush=True)
+    g = zd.ZdTree(dev(P), 16, shift_seed=0)
+    o = oracle.Tree(P, 16, seed=0)
+    gex, oex = g.export(), o.export()
+    for key in ("keys", "ids", "leaf_count", "int_bit"):
+        assert np.array_equal(gex[key], oex[key]), key
+    rows = np.random.default_rng(9).choice(len(P), 5000, replace=False)
+    sel = torch.from_numpy(rows).cuda()
+    for k in (10, 50):
+        ids, d2 = g.knn(k)
+        assert_same_rows((ids[sel], d2[sel]), o.knn_all(k, qids=rows), f"config3 10M k={k}")
+        del ids, d2
+    g.close()
