@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=500_000)
     ap.add_argument("--workload", default="uniform3d",
                     choices=["uniform3d", "spheres", "forest", "grad"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -113,6 +115,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.add(src, 1.0, out=dst)  # one elementwise pass: reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload != "uniform3d":
         {"spheres": bench_spheres, "forest": bench_forest, "grad": bench_grad}[args.workload](args)
         return

@@ -172,9 +172,10 @@ __device__ __forceinline__ double box_dist2(double px, double py, double pz, con
   return s;
 }
 
-// (d, i) < (e, j) in the order on (d2, id)
+// (d, i) < (e, j) in the order on (d2, id).  Bitwise, not short-circuit: the
+// three compares combine as lane masks instead of nested divergent branches.
 __device__ __forceinline__ bool cand_lt(double d, int32_t i, double e, int32_t j) {
-  return d < e || (d == e && i < j);
+  return (d < e) | ((d == e) & (i < j));
 }
 
 // ---------------------------------------------------------------------------

@@ -38,16 +38,18 @@ namespace zd {
 // and never move.  So the k-th entry is always register K-1 and insertion is
 // a branch-free shift with static indices (no dynamic register indexing).
 // While fewer than k candidates have arrived the k-th entry is (+inf,
-// INT_MAX): distance(p, N, k) is infinite and every candidate enters.
+// INT_MAX): distance(p, N, k) is infinite and every candidate enters.  A lane
+// without a query holds (-inf, INT_MIN) everywhere: nothing ever enters and
+// no box is ever within its k-th distance, so it needs no test of its own.
 template <int K>
 struct Heap {
   double d[K];
   int32_t id[K];
 
-  __device__ __forceinline__ void init(int k) {
+  __device__ __forceinline__ void init(int k, bool live) {
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      const bool used = j >= K - k;
+      const bool used = live && j >= K - k;
       d[j] = used ? INFINITY : -INFINITY;
       id[j] = used ? INT_MAX : INT_MIN;
     }
@@ -55,9 +57,12 @@ struct Heap {
 
   __device__ __forceinline__ double kth() const { return d[K - 1]; }
 
-  // insert(N, q, k) of Algorithms 2-3: enters iff it precedes the k-th entry
+  // insert(N, q, k) of Algorithms 2-3: enters iff it precedes the k-th entry.
+  // The first test is one compare; a tie with the k-th distance falls through
+  // to the exact (d2, id) comparisons, which then change nothing if the
+  // candidate does not precede it.
   __device__ __forceinline__ void offer(double dd, int32_t q) {
-    if (!cand_lt(dd, q, d[K - 1], id[K - 1])) return;
+    if (!(dd <= d[K - 1])) return;
     bool lt[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) lt[j] = cand_lt(dd, q, d[j], id[j]);
@@ -106,15 +111,17 @@ struct LdsHeap {
     hi = i;
   }
 
-  __device__ __forceinline__ void init(int k_) {
+  __device__ __forceinline__ void init(int k_, bool live) {
     const int lane = threadIdx.x & 63;
     k = k_;
+    const double d0 = live ? INFINITY : -INFINITY;
+    const int32_t i0 = live ? INT_MAX : INT_MIN;
     for (int s = 0; s < k; ++s) {
-      hd[s * 64 + lane] = INFINITY;
-      hi[s * 64 + lane] = INT_MAX;
+      hd[s * 64 + lane] = d0;
+      hi[s * 64 + lane] = i0;
     }
-    root_d = INFINITY;
-    root_i = INT_MAX;
+    root_d = d0;
+    root_i = i0;
   }
 
   __device__ __forceinline__ double kth() const { return root_d; }
@@ -146,6 +153,7 @@ struct LdsHeap {
   }
 
   __device__ __forceinline__ void offer(double dd, int32_t q) {
+    if (!(dd <= root_d)) return;
     if (!cand_lt(dd, q, root_d, root_i)) return;
     const int lane = threadIdx.x & 63;
     sift(0, k, dd, q);
@@ -225,11 +233,20 @@ struct WaveSearch {
   __device__ __forceinline__ WaveSearch(const TreeView &t_, Cand *stage_) : t(t_), stage(stage_) {}
 
   __device__ __forceinline__ bool wants(const double *lo, const double *hi) const {
-    const bool w = valid && box_dist2<D>(px, py, pz, lo, hi) <= h.kth();
+    const bool w = box_dist2<D>(px, py, pz, lo, hi) <= h.kth();
     return __ballot(w) != 0;
   }
 
-  // every lane scores every point of the leaf (except already-scored ones)
+  __device__ __forceinline__ void score(int32_t from, int32_t to) {
+    for (int32_t jj = from; jj < to; ++jj) {
+      const Cand q = stage[jj];
+      h.offer(dist2<D>(px, py, pz, q.x, q.y, q.z), q.id);
+    }
+  }
+
+  // every lane scores every point of the leaf, except the sorted positions
+  // [skip_lo, skip_hi] already scored (they hold every lane's own point, so
+  // no self test is needed here)
   __device__ __forceinline__ void scan_leaf(int32_t leaf) {
     const int lane = threadIdx.x & 63;
     const int32_t b = uni(t.leaf_begin[leaf]), e = uni(t.leaf_begin[leaf + 1]);
@@ -246,11 +263,13 @@ struct WaveSearch {
       }
       __builtin_amdgcn_wave_barrier();
       const int32_t cnt = min(64, e - c);
-      for (int32_t jj = 0; jj < cnt; ++jj) {
-        if (c + jj >= skip_lo && c + jj <= skip_hi) continue;
-        const Cand q = stage[jj];
-        const double dd = dist2<D>(px, py, pz, q.x, q.y, q.z);
-        if (valid && q.id != self) h.offer(dd, q.id);
+      // skipped local range [sa, sb), empty when sa >= sb
+      const int32_t sa = max(skip_lo - c, 0), sb = min(skip_hi + 1 - c, cnt);
+      if (sa < sb) {
+        score(0, sa);
+        score(sb, cnt);
+      } else {
+        score(0, cnt);
       }
       __builtin_amdgcn_wave_barrier();
     }
@@ -374,7 +393,7 @@ __global__ void __launch_bounds__(256) k_knn_all(TreeView t, int k, int32_t *__r
   s.budget = 4 * t.n + 256;
   s.key_ref = uni((int32_t)(t.key[g0 + mid] >> 32));
   s.key_ref = (s.key_ref << 32) | (uint32_t)uni((int32_t)t.key[g0 + mid]);
-  s.h.init(k);
+  s.h.init(k, s.valid);
   // score the group's own points first (Morton neighbours of every lane)
   {
     Cand q;
@@ -389,12 +408,14 @@ __global__ void __launch_bounds__(256) k_knn_all(TreeView t, int k, int32_t *__r
     for (int jj = 0; jj < cnt; ++jj) {
       const Cand c = s.stage[jj];
       const double dd = dist2<D>(s.px, s.py, s.pz, c.x, c.y, c.z);
-      if (s.valid && jj != lane) s.h.offer(dd, c.id);
+      // the lane's own point enters as (+inf, INT_MAX), which never precedes
+      // the k-th entry
+      s.h.offer(jj == lane ? INFINITY : dd, jj == lane ? INT_MAX : c.id);
     }
     __builtin_amdgcn_wave_barrier();
   }
-  s.skip_lo = (int32_t)g0;
-  s.skip_hi = (int32_t)last;
+  s.skip_lo = uni((int32_t)g0);
+  s.skip_hi = uni((int32_t)last);
   // lowest common ancestor of the group's leaves
   const int32_t lf = uni(t.leaf_of[g0]), ll = uni(t.leaf_of[last]);
   int32_t G = ~lf;
@@ -440,7 +461,7 @@ __global__ void __launch_bounds__(256) k_knn_ext(TreeView t, const double *__res
   s.skip_hi = 0;
   s.key_ref = uni((int32_t)(qkey[g0 + mid] >> 32));
   s.key_ref = (s.key_ref << 32) | (uint32_t)uni((int32_t)qkey[g0 + mid]);
-  s.h.init(k);
+  s.h.init(k, s.valid);
   int32_t node = uni(t.meta[kMetaRoot]);
   if (node != kNoRoot) {
     // descend by the Morton bits (the bit-based search of Section 2) with the
