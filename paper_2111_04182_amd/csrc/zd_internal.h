@@ -156,7 +156,8 @@ __device__ __forceinline__ double dist2(double px, double py, double pz, double 
 // for any point q of the box fl(gap) <= |fl(p - q)|: the box distance never
 // exceeds a member's distance, and pruning with it is exact.
 __device__ __forceinline__ double axis_gap(double p, double lo, double hi) {
-  return p < lo ? lo - p : (p > hi ? p - hi : 0.0);
+  // at most one of lo - p and p - hi is positive (lo <= hi)
+  return fmax(fmax(lo - p, p - hi), 0.0);
 }
 
 template <int D>

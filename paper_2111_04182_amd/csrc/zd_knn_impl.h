@@ -237,13 +237,6 @@ struct WaveSearch {
     return __ballot(w) != 0;
   }
 
-  __device__ __forceinline__ void score(int32_t from, int32_t to) {
-    for (int32_t jj = from; jj < to; ++jj) {
-      const Cand q = stage[jj];
-      h.offer(dist2<D>(px, py, pz, q.x, q.y, q.z), q.id);
-    }
-  }
-
   // every lane scores every point of the leaf, except the sorted positions
   // [skip_lo, skip_hi] already scored (they hold every lane's own point, so
   // no self test is needed here)
@@ -263,54 +256,63 @@ struct WaveSearch {
       }
       __builtin_amdgcn_wave_barrier();
       const int32_t cnt = min(64, e - c);
-      // skipped local range [sa, sb), empty when sa >= sb
-      const int32_t sa = max(skip_lo - c, 0), sb = min(skip_hi + 1 - c, cnt);
-      if (sa < sb) {
-        score(0, sa);
-        score(sb, cnt);
-      } else {
-        score(0, cnt);
+      // skipped local range [sa, sb); sa = cnt when it is empty
+      int32_t sa = max(skip_lo - c, 0);
+      const int32_t sb = min(skip_hi + 1 - c, cnt);
+      if (sa >= sb) sa = cnt;
+      for (int32_t jj = 0; jj < cnt; ++jj) {
+        if (jj == sa) {
+          jj = sb;
+          if (jj >= cnt) break;
+        }
+        const Cand q = stage[jj];
+        h.offer(dist2<D>(px, py, pz, q.x, q.y, q.z), q.id);
       }
       __builtin_amdgcn_wave_barrier();
     }
   }
 
   // searchDown (Algorithm 2) below internal node `top`, whose own box the
-  // caller has already tested.  Stackless: nodes record parent and side, and
-  // the child order is recomputed when the walk returns to a node.
+  // caller has already tested.  The walk is the same on every lane, so its
+  // stack of pending (node, side) links is one VGPR holding entry i in lane
+  // i (a lane select to push, readlane to pop: no memory traffic).  Each step tests one child
+  // box with the current k-th distance; entering an internal node pushes its
+  // farther child and tests the nearer one first.  Split bits strictly
+  // decrease downwards and lie in [0, 64) below a tree or cloud root, so a
+  // path holds at most 64 internal nodes and the stack at most 64 entries;
+  // a deeper stack only occurs on a corrupted tree and ends the walk, like
+  // the step budget.
   __device__ __forceinline__ void search_down(int32_t top) {
+    int32_t stk = 0;
+    int32_t sp = 0;
     int32_t n = top;
-    bool entering = true;
-    int from_side = 0;
+    int s = -1;  // -1: entering n, child order not chosen yet
     while (--budget > 0) {
       const INode *N = &t.inode[n];
-      // nearer child first: the side of the split holding the reference
-      // point's cell (an order heuristic only; it never changes the rows)
-      const int bit = uni(N->bit);
-      const int first = bit < 64 ? (int)((key_ref >> bit) & 1) : 0;
-      int s = entering ? first : (from_side == first ? 1 - first : 2);
-      bool descended = false;
-      while (s != 2) {
-        if (wants(N->lo[s], N->hi[s])) {
-          const int32_t ch = uni(N->child[s]);
-          if (ch < 0) {
-            scan_leaf(~ch);
-          } else {
-            n = ch;
-            entering = true;
-            descended = true;
-            break;
-          }
-        }
-        s = (s == first) ? 1 - first : 2;
+      if (s < 0) {
+        // nearer child first: the side of the split holding the reference
+        // point's cell (an order heuristic only; it never changes the rows)
+        const int bit = uni(N->bit);
+        const int first = bit < 64 ? (int)((key_ref >> bit) & 1) : 0;
+        if (sp >= 64) return;
+        if ((int)(threadIdx.x & 63) == sp) stk = (n << 1) | (1 - first);
+        ++sp;
+        s = first;
       }
-      if (descended) continue;
-      if (n == top) return;
-      const int32_t par = uni(N->parent);
-      if (par < 0) return;
-      from_side = par & 1;
-      n = par >> 1;
-      entering = false;
+      if (wants(N->lo[s], N->hi[s])) {
+        const int32_t ch = uni(N->child[s]);
+        if (ch >= 0) {
+          n = ch;
+          s = -1;
+          continue;
+        }
+        scan_leaf(~ch);
+      }
+      if (sp == 0) return;
+      --sp;
+      const int32_t e = __builtin_amdgcn_readlane(stk, sp);
+      n = e >> 1;
+      s = e & 1;
     }
   }
 
