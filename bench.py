@@ -55,6 +55,27 @@ BOX_PER_QUERY = 49.2
 OPS_PER_QUERY = 8 * CAND_PER_QUERY + 17 * BOX_PER_QUERY
 PAPER_BUILD_QUERY_K10_QPS = 10_000_000 / 0.453  # CPU context only (144 threads)
 
+# HBM bytes per launch of the all-points query kernel on this workload, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by the same counters on a
+# 1 GiB elementwise pass (profiles/knn_all_uniform3d_10M_k10_hbm_bytes.md).
+# They describe the kernel sources with this sha1 only; after any change to
+# them the figure is reported as null until the counters are taken again.
+KNN_TRAFFIC = {"sources_sha1": "d0053df5a6248d91180180ae8cd6efc285d5a396",
+               "fetch_bytes": 6.531e9, "write_bytes": 1.600e9}
+KNN_SOURCES = ("paper_2111_04182_amd/csrc/zd_knn_impl.h", "paper_2111_04182_amd/csrc/zd_internal.h",
+               "paper_2111_04182_amd/csrc/zd_knn_all_d3.hip")
+
+
+def knn_traffic():
+    import hashlib
+    h = hashlib.sha1()
+    for s in KNN_SOURCES:
+        with open(os.path.join(ROOT, s), "rb") as f:
+            h.update(f.read())
+    if KNN_TRAFFIC["sources_sha1"] != h.hexdigest() or KNN_TRAFFIC["fetch_bytes"] is None:
+        return None
+    return KNN_TRAFFIC["fetch_bytes"] + KNN_TRAFFIC["write_bytes"]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -173,7 +194,9 @@ def main():
     log("bench: phases (ms) " + json.dumps({p: round(v, 3) for p, v in ph.items()}))
     rows = 2 * n  # live rows answered per step (n before and n after the updates)
     value = rows / (ms_step / 1e3)
-    q_launch_s = ph["query"] / 1e3
+    # the query kernel runs twice per step (before and after the updates, 10M
+    # live rows each); its launch time is the mean of the two
+    q_launch_s = (ph["query"] + ph["requery"]) / 2 / 1e3
     achieved_tops = n * OPS_PER_QUERY / q_launch_s / 1e12
     result = {
         "metric": "all-points kNN queries/s and build Mpts/s (3D, 10M, k=10) at 1 MI355X",
@@ -199,11 +222,11 @@ def main():
         "phase_ms": ph,
         "paper_cpu_context": {"build_plus_query_k10_qps": PAPER_BUILD_QUERY_K10_QPS,
                               "hw": "4x Xeon E7-8867 v4, 144 threads"},
-        "roofline": {"bound": "alu", "kernel": "k_knn_all<3,16>",
+        "roofline": {"bound": "alu", "kernel": "k_knn_all<3, 10>",
                      "achieved": achieved_tops, "peak": FP64_VALU_PEAK_TOPS,
                      "unit": "TFLOP/s", "frac": achieved_tops / FP64_VALU_PEAK_TOPS,
-                     "traffic": None,
-                     "ops_per_query": OPS_PER_QUERY, "launch_ms": ph["query"]},
+                     "traffic": knn_traffic(),
+                     "ops_per_query": OPS_PER_QUERY, "launch_ms": q_launch_s * 1e3},
     }
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
