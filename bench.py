@@ -47,12 +47,20 @@ sys.path.insert(0, ROOT)
 FP64_VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 # Algorithmic FP64 work per all-points query on this workload (3D uniform,
-# 10M points, L = 16, k = 10), from the oracle's counters over 200,000
-# queries: 92.0 candidate distances (8 ops each: 3 sub, 3 mul, 2 add) and
-# 49.2 box tests (17 ops each: 3 clamps/subs, 3 mul, 2 add, compares).
-CAND_PER_QUERY = 92.0
-BOX_PER_QUERY = 49.2
-OPS_PER_QUERY = 8 * CAND_PER_QUERY + 17 * BOX_PER_QUERY
+# 10M points, k = 10), by leaf size: mean candidate distances (8 ops each:
+# 3 sub, 3 mul, 2 add) and box tests (17 ops each) of the serial oracle's
+# leaf-based search over 200,000 evenly spaced ids, printed by
+# `python oracle/work_counters.py --leaf L`.
+WORK_PER_QUERY = {8: (59.59, 64.24), 16: (92.0, 49.21), 24: (120.42, 41.3), 32: (134.92, 38.39)}
+
+
+def ops_per_query(leaf):
+    if leaf not in WORK_PER_QUERY:
+        return None
+    cand, box = WORK_PER_QUERY[leaf]
+    return 8 * cand + 17 * box
+
+
 PAPER_BUILD_QUERY_K10_QPS = 10_000_000 / 0.453  # CPU context only (144 threads)
 
 # HBM bytes per launch of the all-points query kernel on this workload, from
@@ -62,6 +70,7 @@ PAPER_BUILD_QUERY_K10_QPS = 10_000_000 / 0.453  # CPU context only (144 threads)
 # them the figure is reported as null until the counters are taken again.
 KNN_TRAFFIC = {"sources_sha1": "d0053df5a6248d91180180ae8cd6efc285d5a396",
                "fetch_bytes": 6.531e9, "write_bytes": 1.600e9}
+TRAFFIC_LEAF = 16  # leaf size of the profiled run
 KNN_SOURCES = ("paper_2111_04182_amd/csrc/zd_knn_impl.h", "paper_2111_04182_amd/csrc/zd_internal.h",
                "paper_2111_04182_amd/csrc/zd_knn_all_d3.hip")
 
@@ -81,13 +90,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(P, n_sample: int):
+def cpu_baseline(P, n_sample: int, leaf: int):
     """The oracle as it stands (serial C), on a bounded sample of the same
     workload: a full serial build of all n points, then the leaf-based search
     for n_sample of them (every (n / n_sample)-th id)."""
     import oracle
     t0 = time.perf_counter()
-    tr = oracle.Tree(P, 16, box=(np.zeros(3), np.ones(3)), seed=0)
+    tr = oracle.Tree(P, leaf, box=(np.zeros(3), np.ones(3)), seed=0)
     t_build = time.perf_counter() - t0
     qids = np.arange(0, P.shape[0], P.shape[0] // n_sample)[:n_sample]
     t0 = time.perf_counter()
@@ -197,7 +206,8 @@ def main():
     # the query kernel runs twice per step (before and after the updates, 10M
     # live rows each); its launch time is the mean of the two
     q_launch_s = (ph["query"] + ph["requery"]) / 2 / 1e3
-    achieved_tops = n * OPS_PER_QUERY / q_launch_s / 1e12
+    opq = ops_per_query(L) if (n, k) == (10_000_000, 10) else None
+    achieved_tops = n * opq / q_launch_s / 1e12 if opq else None
     result = {
         "metric": "all-points kNN queries/s and build Mpts/s (3D, 10M, k=10) at 1 MI355X",
         "value": value,
@@ -222,15 +232,20 @@ def main():
         "phase_ms": ph,
         "paper_cpu_context": {"build_plus_query_k10_qps": PAPER_BUILD_QUERY_K10_QPS,
                               "hw": "4x Xeon E7-8867 v4, 144 threads"},
-        "roofline": {"bound": "alu", "kernel": "k_knn_all<3, 10>",
+        "roofline": {"bound": "alu", "kernel": f"k_knn_all<3, {k}>",
                      "achieved": achieved_tops, "peak": FP64_VALU_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tops / FP64_VALU_PEAK_TOPS,
-                     "traffic": knn_traffic(),
-                     "ops_per_query": OPS_PER_QUERY, "launch_ms": q_launch_s * 1e3},
+                     "unit": "TFLOP/s",
+                     "frac": achieved_tops / FP64_VALU_PEAK_TOPS if achieved_tops else None,
+                     "traffic": knn_traffic() if (n, k, L) == (10_000_000, 10, TRAFFIC_LEAF) else None,
+                     "ops_per_query": opq, "launch_ms": q_launch_s * 1e3,
+                     # the same launches against the HBM roofline: compulsory bytes
+                     # per query = 24 B coordinates + 4 B id map + 12 B per
+                     # neighbour written (the tree's nodes add < 2%)
+                     "hbm_frac": n * (28 + 12 * k) / q_launch_s / (HBM_PEAK_GBS * 1e9)},
     }
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
-        tr, qids, want, cb = cpu_baseline(P, args.cpu_sample)
+        tr, qids, want, cb = cpu_baseline(P, args.cpu_sample, L)
         result["cpu_baseline"] = cb
         # verification outside the timed region: sampled rows of the first query
         chk = qids[:: max(1, len(qids) // 2000)]

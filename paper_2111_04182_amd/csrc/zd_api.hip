@@ -564,7 +564,7 @@ struct zd_forest_s {
   int32_t *seg_leaf = nullptr;  // device [C] or null (one leaf size)
   int4 *tiles = nullptr;        // sort tiles, none spanning two clouds
   int ntiles = 0;
-  int2 *groups = nullptr;       // query groups, none spanning two clouds
+  int4 *groups = nullptr;       // query groups (first, last, cloud first, cloud last)
   int64_t ngroups = 0;
   // captured build + query
   hipStream_t cap = nullptr;
@@ -647,7 +647,7 @@ zd_status forest_setup(const zd_params *p, const double *xyz, int64_t n, const i
   }
   // tile and group tables
   std::vector<int4> tiles;
-  std::vector<int2> groups;
+  std::vector<int4> groups;
   for (int32_t c = 0; c < C; ++c) {
     const int64_t a = offsets[c], b = offsets[c + 1], m = b - a;
     const int nts = (int)((m + 4095) / 4096);
@@ -658,7 +658,7 @@ zd_status forest_setup(const zd_params *p, const double *xyz, int64_t n, const i
                                 nts));
     }
     for (int64_t g = a; g < b; g += 64)
-      groups.push_back(make_int2((int)g, (int)std::min<int64_t>(g + 63, b - 1)));
+      groups.push_back(make_int4((int)g, (int)std::min<int64_t>(g + 63, b - 1), (int)a, (int)(b - 1)));
   }
   f->ntiles = (int)tiles.size();
   f->ngroups = (int64_t)groups.size();
@@ -682,7 +682,7 @@ zd_status forest_setup(const zd_params *p, const double *xyz, int64_t n, const i
   if (e == hipSuccess && f->ntiles)
     e = hipMemcpy(f->tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && f->ngroups)
-    e = hipMemcpy(f->groups, groups.data(), sizeof(int2) * groups.size(), hipMemcpyHostToDevice);
+    e = hipMemcpy(f->groups, groups.data(), sizeof(int4) * groups.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     forest_destroy(f);
     return to_status(e);

@@ -7,9 +7,9 @@
 namespace zd {
 
 hipError_t knn_all_d2(const TreeView &t, int k, int32_t *ids, double *d2, hipStream_t s,
-                      const int2 *groups, int64_t ngroups);
+                      const int4 *groups, int64_t ngroups);
 hipError_t knn_all_d3(const TreeView &t, int k, int32_t *ids, double *d2, hipStream_t s,
-                      const int2 *groups, int64_t ngroups);
+                      const int4 *groups, int64_t ngroups);
 hipError_t knn_ext_d2(const TreeView &t, const double *q, const uint64_t *qkey,
                       const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
                       hipStream_t s);
@@ -18,7 +18,7 @@ hipError_t knn_ext_d3(const TreeView &t, const double *q, const uint64_t *qkey,
                       hipStream_t s);
 
 hipError_t knn_all_points(int dim, const TreeView &t, int k, int32_t *out_ids, double *out_d2,
-                          hipStream_t s, const int2 *groups, int64_t ngroups) {
+                          hipStream_t s, const int4 *groups, int64_t ngroups) {
   if (t.n <= 0 || (groups && ngroups <= 0)) return hipSuccess;
   return dim == 3 ? knn_all_d3(t, k, out_ids, out_d2, s, groups, ngroups)
                   : knn_all_d2(t, k, out_ids, out_d2, s, groups, ngroups);

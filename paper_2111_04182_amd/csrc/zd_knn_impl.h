@@ -22,9 +22,10 @@
 //   * node records are read at wave-uniform addresses, and a visited leaf's
 //     points are staged once in LDS and broadcast to all lanes, so the walk
 //     itself never diverges;
-//   * for all-points rows, each lane first scores the group's own 64 points
-//     (its Morton neighbours), which tightens every lane's k-th distance
-//     before the walk starts; those positions are skipped later.
+//   * for all-points rows, each lane first scores the group's own points and
+//     the 32 sorted positions on either side (its Morton neighbours), which
+//     tightens every lane's k-th distance before the walk starts; those
+//     positions are skipped later.
 #pragma once
 
 #include "zd_internal.h"
@@ -211,6 +212,9 @@ __device__ __forceinline__ bool ball_inside(double px, double py, double pz, con
 
 __device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// sorted positions scored on either side of a query group before its walk
+constexpr int64_t kPrescore = 32;
+
 // one staged candidate point (32 bytes: two 16-byte LDS reads)
 struct Cand {
   double x, y, z;
@@ -235,6 +239,38 @@ struct WaveSearch {
   __device__ __forceinline__ bool wants(const double *lo, const double *hi) const {
     const bool w = box_dist2<D>(px, py, pz, lo, hi) <= h.kth();
     return __ballot(w) != 0;
+  }
+
+  // Every lane scores the sorted positions [a, b] (64 at a time through LDS)
+  // and the walk then skips them.  `own` is this lane's own sorted position,
+  // which enters as (+inf, INT_MAX) and so never precedes the k-th entry.
+  // (External query groups cover many more tree points than their 64
+  // queries, and measured slower with a prescored window.)
+  __device__ __forceinline__ void prescore(int64_t a, int64_t b, int64_t own) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t c = a; c <= b; c += 64) {
+      const int64_t j = c + lane;
+      if (j <= b) {
+        Cand q;
+        q.x = t.X[j];
+        q.y = t.Y[j];
+        q.z = D == 3 ? t.Z[j] : 0.0;
+        q.id = t.id[j];
+        q.pad = 0;
+        stage[lane] = q;
+      }
+      __builtin_amdgcn_wave_barrier();
+      const int cnt = (int)min((int64_t)64, b - c + 1);
+      const int me = own >= c && own < c + 64 ? (int)(own - c) : -1;
+      for (int jj = 0; jj < cnt; ++jj) {
+        const Cand q = stage[jj];
+        const double dd = dist2<D>(px, py, pz, q.x, q.y, q.z);
+        h.offer(jj == me ? INFINITY : dd, jj == me ? INT_MAX : q.id);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    skip_lo = uni((int32_t)a);
+    skip_hi = uni((int32_t)b);
   }
 
   // every lane scores every point of the leaf, except the sorted positions
@@ -344,6 +380,21 @@ struct WaveSearch {
   }
 };
 
+// Workgroups are dealt to the chip's 8 XCDs round-robin (workgroup h runs on
+// XCD h mod 8), and every XCD has its own L2.  This maps hardware workgroup h
+// to a logical one so that each XCD takes one contiguous run of logical
+// workgroups: neighbouring query groups share most of their nodes and
+// leaves, which then stay in one L2 instead of being fetched by all eight.
+// The map is a bijection on [0, nb): XCD x owns nb/8 logical workgroups,
+// plus one if x < nb mod 8.  (Used for all-points rows, where it cuts the
+// query's L2-miss traffic about fourfold; external queries measured slower
+// with it and keep the plain order.)
+__device__ __forceinline__ uint32_t xcd_block(uint32_t h, uint32_t nb) {
+  constexpr uint32_t kXcd = 8;
+  const uint32_t x = h % kXcd, local = h / kXcd, q = nb / kXcd, r = nb % kXcd;
+  return x * q + min(x, r) + local;
+}
+
 // All-points rows: wavefront w answers sorted positions [64w, 64w + 64).
 // LDS per wavefront: the 64-entry candidate stage, plus the heap for large k
 template <int K>
@@ -368,20 +419,24 @@ __device__ __forceinline__ void bind_lds(WaveSearch<D, K> &s, char *smem, int w)
 template <int D, int K>
 __global__ void __launch_bounds__(256) k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
                                                  double *__restrict__ out_d2,
-                                                 const int2 *__restrict__ groups, int64_t ngroups) {
+                                                 const int4 *__restrict__ groups, int64_t ngroups) {
   extern __shared__ __align__(16) char smem[];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int64_t gw = (int64_t)blockIdx.x * waves_per_block<K>() + w;
-  int64_t g0, last;
+  const int64_t gw = (int64_t)xcd_block(blockIdx.x, gridDim.x) * waves_per_block<K>() + w;
+  int64_t g0, last, c_lo, c_hi;  // the group, and the cloud that holds it
   if (groups) {
     if (gw >= ngroups) return;
     g0 = uni(groups[gw].x);
     last = uni(groups[gw].y);
+    c_lo = uni(groups[gw].z);
+    c_hi = uni(groups[gw].w);
   } else {
     g0 = gw * 64;
     if (g0 >= t.n) return;
     last = min(g0 + 63, t.n - 1);
+    c_lo = 0;
+    c_hi = t.n - 1;
   }
   const int64_t i = min(g0 + lane, last);
   WaveSearch<D, K> s(t, nullptr);
@@ -396,28 +451,11 @@ __global__ void __launch_bounds__(256) k_knn_all(TreeView t, int k, int32_t *__r
   s.key_ref = uni((int32_t)(t.key[g0 + mid] >> 32));
   s.key_ref = (s.key_ref << 32) | (uint32_t)uni((int32_t)t.key[g0 + mid]);
   s.h.init(k, s.valid);
-  // score the group's own points first (Morton neighbours of every lane)
-  {
-    Cand q;
-    q.x = s.px;
-    q.y = s.py;
-    q.z = s.pz;
-    q.id = s.self;
-    q.pad = 0;
-    s.stage[lane] = q;
-    __builtin_amdgcn_wave_barrier();
-    const int cnt = (int)(last - g0 + 1);
-    for (int jj = 0; jj < cnt; ++jj) {
-      const Cand c = s.stage[jj];
-      const double dd = dist2<D>(s.px, s.py, s.pz, c.x, c.y, c.z);
-      // the lane's own point enters as (+inf, INT_MAX), which never precedes
-      // the k-th entry
-      s.h.offer(jj == lane ? INFINITY : dd, jj == lane ? INT_MAX : c.id);
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-  s.skip_lo = uni((int32_t)g0);
-  s.skip_hi = uni((int32_t)last);
+  // score first the sorted positions around the group, within its cloud:
+  // the group's own points and kPrescore on either side (Morton neighbours
+  // of every lane).  This tightens every lane's k-th distance before the
+  // walk, which then skips these positions.
+  s.prescore(max(c_lo, g0 - kPrescore), min(c_hi, last + kPrescore), g0 + lane);
   // lowest common ancestor of the group's leaves
   const int32_t lf = uni(t.leaf_of[g0]), ll = uni(t.leaf_of[last]);
   int32_t G = ~lf;
@@ -484,7 +522,7 @@ __global__ void __launch_bounds__(256) k_knn_ext(TreeView t, const double *__res
 
 template <int D, int K>
 hipError_t launch_knn_all(const TreeView &t, int k, int32_t *ids, double *d2, hipStream_t s,
-                          const int2 *groups, int64_t ngroups) {
+                          const int4 *groups, int64_t ngroups) {
   const int64_t waves = groups ? ngroups : (t.n + 63) / 64;
   constexpr int wpb = waves_per_block<K>();
   k_knn_all<D, K><<<(unsigned)((waves + wpb - 1) / wpb), 64 * wpb, wpb * wave_lds_bytes<K>(), s>>>(
