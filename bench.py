@@ -68,8 +68,8 @@ PAPER_BUILD_QUERY_K10_QPS = 10_000_000 / 0.453  # CPU context only (144 threads)
 # 1 GiB elementwise pass (profiles/knn_all_uniform3d_10M_k10_hbm_bytes.md).
 # They describe the kernel sources with this sha1 only; after any change to
 # them the figure is reported as null until the counters are taken again.
-KNN_TRAFFIC = {"sources_sha1": "d0053df5a6248d91180180ae8cd6efc285d5a396",
-               "fetch_bytes": 6.531e9, "write_bytes": 1.600e9}
+KNN_TRAFFIC = {"sources_sha1": "96fad49592a75ea6e37d15a7dcaae777750656db",
+               "fetch_bytes": 1.539e9, "write_bytes": 1.601e9}
 TRAFFIC_LEAF = 16  # leaf size of the profiled run
 KNN_SOURCES = ("paper_2111_04182_amd/csrc/zd_knn_impl.h", "paper_2111_04182_amd/csrc/zd_internal.h",
                "paper_2111_04182_amd/csrc/zd_knn_all_d3.hip")
