@@ -284,14 +284,17 @@ zd_status zd_build(const zd_params *p, const double *xyz, int64_t n, void *strea
   if (e == hipSuccess) e = store_alloc(t->st, n, dim, s);
   uint64_t *ktmp = nullptr;
   int32_t *itmp = nullptr;
+  double *aos = nullptr;  // the points as records, for the gather after the sort
   if (e == hipSuccess && n > 1) e = dev_alloc_n(&ktmp, n, s);
   if (e == hipSuccess && n > 1) e = dev_alloc_n(&itmp, n, s);
-  if (e == hipSuccess) e = encode_keys(t->geo, xyz, n, n, 0, t->st.key, t->st.id, s);
+  if (e == hipSuccess && n > 0) e = dev_alloc_n(&aos, n * (dim == 3 ? 4 : 2), s);
+  if (e == hipSuccess) e = encode_keys(t->geo, xyz, n, n, 0, t->st.key, t->st.id, s, aos);
   if (e == hipSuccess) e = radix_sort_pairs(t->st.key, t->st.id, ktmp, itmp, n, dim * B, s);
   dev_release(ktmp, s);
   dev_release(itmp, s);
   if (e == hipSuccess)
-    e = gather_points(dim, xyz, n, t->st.id, n, t->st.X, t->st.Y, t->st.Z, t->slot_of, s);
+    e = gather_points(dim, xyz, n, t->st.id, n, t->st.X, t->st.Y, t->st.Z, t->slot_of, s, aos);
+  dev_release(aos, s);
   if (e == hipSuccess) e = relink(t);
   if (e != hipSuccess) {
     destroy(t);

@@ -34,25 +34,35 @@ namespace zd {
 
 // ----------------------------------------------------------------- encode --
 
+// points per record of the AoS staging copy: 4 doubles (32 B) in 3-D, 2 in 2-D
+template <int D>
+constexpr int kAos = D == 3 ? 4 : 2;
+
 template <int D>
 __global__ void k_encode(Geometry g, const double *__restrict__ xyz, int64_t stride, int64_t n,
-                         int32_t id_base, uint64_t *__restrict__ key, int32_t *__restrict__ id) {
+                         int32_t id_base, uint64_t *__restrict__ key, int32_t *__restrict__ id,
+                         double *__restrict__ aos) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double x = xyz[i], y = xyz[stride + i];
   double z = D == 3 ? xyz[2 * stride + i] : 0.0;
   key[i] = morton_key<D>(g, x, y, z);
   id[i] = id_base + (int32_t)i;
+  if (aos) {
+    double2 *r = reinterpret_cast<double2 *>(aos + (int64_t)kAos<D> * i);
+    r[0] = make_double2(x, y);
+    if (D == 3) r[1] = make_double2(z, 0.0);
+  }
 }
 
 hipError_t encode_keys(const Geometry &g, const double *xyz, int64_t stride, int64_t n,
-                       int32_t id_base, uint64_t *key, int32_t *id, hipStream_t s) {
+                       int32_t id_base, uint64_t *key, int32_t *id, hipStream_t s, double *aos) {
   if (n <= 0) return hipSuccess;
   unsigned grid = (unsigned)((n + 255) / 256);
   if (g.dim == 3)
-    k_encode<3><<<grid, 256, 0, s>>>(g, xyz, stride, n, id_base, key, id);
+    k_encode<3><<<grid, 256, 0, s>>>(g, xyz, stride, n, id_base, key, id, aos);
   else
-    k_encode<2><<<grid, 256, 0, s>>>(g, xyz, stride, n, id_base, key, id);
+    k_encode<2><<<grid, 256, 0, s>>>(g, xyz, stride, n, id_base, key, id, aos);
   return hipGetLastError();
 }
 
@@ -166,25 +176,33 @@ template <int D>
 __global__ void k_gather(const double *__restrict__ xyz, int64_t stride,
                          const int32_t *__restrict__ id, int64_t n, double *__restrict__ X,
                          double *__restrict__ Y, double *__restrict__ Z,
-                         int32_t *__restrict__ slot_of) {
+                         int32_t *__restrict__ slot_of, const double *__restrict__ aos) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int32_t src = id[i];
-  X[i] = xyz[src];
-  Y[i] = xyz[stride + src];
-  if (D == 3) Z[i] = xyz[2 * stride + src];
+  if (aos) {
+    const double2 *r = reinterpret_cast<const double2 *>(aos + (int64_t)kAos<D> * src);
+    const double2 a = r[0];
+    X[i] = a.x;
+    Y[i] = a.y;
+    if (D == 3) Z[i] = r[1].x;
+  } else {
+    X[i] = xyz[src];
+    Y[i] = xyz[stride + src];
+    if (D == 3) Z[i] = xyz[2 * stride + src];
+  }
   slot_of[src] = (int32_t)i;
 }
 
 hipError_t gather_points(int dim, const double *xyz, int64_t stride, const int32_t *id,
                          int64_t n, double *X, double *Y, double *Z, int32_t *slot_of,
-                         hipStream_t s) {
+                         hipStream_t s, const double *aos) {
   if (n <= 0) return hipSuccess;
   unsigned grid = (unsigned)((n + 255) / 256);
   if (dim == 3)
-    k_gather<3><<<grid, 256, 0, s>>>(xyz, stride, id, n, X, Y, Z, slot_of);
+    k_gather<3><<<grid, 256, 0, s>>>(xyz, stride, id, n, X, Y, Z, slot_of, aos);
   else
-    k_gather<2><<<grid, 256, 0, s>>>(xyz, stride, id, n, X, Y, Z, slot_of);
+    k_gather<2><<<grid, 256, 0, s>>>(xyz, stride, id, n, X, Y, Z, slot_of, aos);
   return hipGetLastError();
 }
 
@@ -266,13 +284,55 @@ __device__ __forceinline__ double fetch_f64(double *p) {
 __device__ __forceinline__ void publish_i32(int32_t *p, int32_t v) { atomicExch(p, v); }
 __device__ __forceinline__ int32_t fetch_i32(int32_t *p) { return atomicOr(p, 0); }
 
+constexpr int kLeafBlock = 256;
+
+// One thread per leaf: the leaf's point range and tight box, then the climb.
+// A node spanning leaves [l, r] hangs below the neighbouring split (l-1 or r)
+// with the lower bit; each node is finished by the second child to arrive.
+// Workgroup w takes leaves [256w, 256w + 256).  An internal node whose whole
+// leaf range lies in that window ("local": its nearest higher splits on both
+// sides lie in the window, found by a scan of the window's split bits in
+// LDS) has both children climbed by this workgroup, so its two children meet
+// in LDS; only the nodes above a window's local subtrees meet through device
+// memory.
 template <int D>
-__global__ void k_leaves(const double *__restrict__ X, const double *__restrict__ Y,
-                         const double *__restrict__ Z, int64_t n, INode *inode, int32_t *meta,
-                         int32_t *__restrict__ leaf_begin, int32_t *leaf_parent,
-                         int32_t *__restrict__ leaf_of, double *root_box) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kLeafBlock)
+    k_leaves(const double *__restrict__ X, const double *__restrict__ Y,
+             const double *__restrict__ Z, int64_t n, INode *inode, int32_t *meta,
+             int32_t *__restrict__ leaf_begin, int32_t *leaf_parent,
+             int32_t *__restrict__ leaf_of, double *root_box) {
+  __shared__ int32_t s_bit[kLeafBlock + 1];  // split bits of nodes j0-1 .. j0+255
+  __shared__ int32_t s_loc[kLeafBlock];      // node j0+t is local
+  __shared__ int32_t s_cnt[kLeafBlock];      // arrivals at local node j0+t
+  __shared__ int32_t s_end[kLeafBlock][2];   // outer leaf bound of each child
+  __shared__ double s_box[kLeafBlock][2][6]; // box of each child (lo, hi)
+  const int t = threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * kLeafBlock;
   const int32_t I = meta[kMetaInternal];
+  if (j0 > I) return;
+  // nodes outside [0, I) act as splits above every bit: the tree's ends
+  for (int q = t; q <= kLeafBlock; q += kLeafBlock) {
+    const int64_t x = j0 - 1 + q;
+    s_bit[q] = (x >= 0 && x < I) ? inode[x].bit : INT_MAX;
+  }
+  s_cnt[t] = 0;
+  __syncthreads();
+  {
+    // node x = j0 + t splits leaves x and x+1; its range ends at the nearest
+    // higher split on each side (LDS index q holds node j0 - 1 + q)
+    bool loc = false;
+    const int64_t x = j0 + t;
+    if (x < I && t < kLeafBlock - 1) {
+      const int32_t bx = s_bit[t + 1];
+      bool lok = false, rok = false;
+      for (int q = t; q >= 0 && !lok; --q) lok = s_bit[q] > bx;
+      for (int q = t + 2; q <= kLeafBlock && !rok; ++q) rok = s_bit[q] > bx;
+      loc = lok && rok;
+    }
+    s_loc[t] = loc ? 1 : 0;
+  }
+  __syncthreads();
+  const int64_t j = j0 + t;
   if (j > I) return;
   const int32_t begin = j == 0 ? 0 : inode[j - 1].split + 1;
   const int32_t end = j == I ? (int32_t)n : inode[j].split + 1;
@@ -290,8 +350,10 @@ __global__ void k_leaves(const double *__restrict__ X, const double *__restrict_
       lo[2] = fmin(lo[2], z); hi[2] = fmax(hi[2], z);
     }
   }
-  // climb: a node spanning leaves [l, r] hangs below the neighbouring split
-  // (l-1 or r) with the lower bit
+  auto bit_of = [&](int32_t x) -> int32_t {
+    const int64_t q = (int64_t)x - (j0 - 1);
+    return (q >= 0 && q <= kLeafBlock) ? s_bit[q] : inode[x].bit;
+  };
   int32_t l = (int32_t)j, r = (int32_t)j;
   int32_t node = ~(int32_t)j;
   for (int guard = 0; guard < 130; ++guard) {
@@ -307,7 +369,7 @@ __global__ void k_leaves(const double *__restrict__ X, const double *__restrict_
     if (l == 0) { p = r; side = 0; }
     else if (r == I) { p = l - 1; side = 1; }
     else {
-      side = inode[r].bit < inode[l - 1].bit ? 0 : 1;
+      side = bit_of(r) < bit_of(l - 1) ? 0 : 1;
       p = side ? l - 1 : r;
     }
     INode *P = &inode[p];
@@ -315,21 +377,43 @@ __global__ void k_leaves(const double *__restrict__ X, const double *__restrict_
     P->child[side] = node;
     if (node < 0) leaf_parent[~node] = (p << 1) | side;
     else inode[node].parent = (p << 1) | side;
-    // what the sibling needs now: this child's box and outer bound
-    for (int c = 0; c < 3; ++c) {
-      publish_f64(&P->lo[side][c], lo[c]);
-      publish_f64(&P->hi[side][c], hi[c]);
-    }
-    publish_i32(side == 0 ? &P->first_leaf : &P->last_leaf, side == 0 ? l : r);
-    // every publish has completed before the arrival is counted
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    if (atomicAdd(&P->visits, 1) == 0) break;  // the sibling finishes this node
     const int os = 1 - side;
-    for (int c = 0; c < 3; ++c) {
-      lo[c] = fmin(lo[c], fetch_f64(&P->lo[os][c]));
-      hi[c] = fmax(hi[c], fetch_f64(&P->hi[os][c]));
+    const int64_t qp = (int64_t)p - j0;
+    if (qp >= 0 && qp < kLeafBlock && s_loc[qp]) {
+      // both children of p are climbed in this workgroup: meet in LDS
+      for (int c = 0; c < 3; ++c) {
+        P->lo[side][c] = lo[c];
+        P->hi[side][c] = hi[c];
+        s_box[qp][side][c] = lo[c];
+        s_box[qp][side][3 + c] = hi[c];
+      }
+      if (side == 0) P->first_leaf = l; else P->last_leaf = r;
+      s_end[qp][side] = side == 0 ? l : r;
+      // the box is in LDS before the arrival is counted; the second arrival
+      // reads the sibling's box after its count
+      if (__hip_atomic_fetch_add(&s_cnt[qp], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
+        break;
+      for (int c = 0; c < 3; ++c) {
+        lo[c] = fmin(lo[c], s_box[qp][os][c]);
+        hi[c] = fmax(hi[c], s_box[qp][os][3 + c]);
+      }
+      if (side == 0) r = s_end[qp][os]; else l = s_end[qp][os];
+    } else {
+      // what the sibling needs now: this child's box and outer bound
+      for (int c = 0; c < 3; ++c) {
+        publish_f64(&P->lo[side][c], lo[c]);
+        publish_f64(&P->hi[side][c], hi[c]);
+      }
+      publish_i32(side == 0 ? &P->first_leaf : &P->last_leaf, side == 0 ? l : r);
+      // every publish has completed before the arrival is counted
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      if (atomicAdd(&P->visits, 1) == 0) break;  // the sibling finishes this node
+      for (int c = 0; c < 3; ++c) {
+        lo[c] = fmin(lo[c], fetch_f64(&P->lo[os][c]));
+        hi[c] = fmax(hi[c], fetch_f64(&P->hi[os][c]));
+      }
+      if (side == 0) r = fetch_i32(&P->last_leaf); else l = fetch_i32(&P->first_leaf);
     }
-    if (side == 0) r = fetch_i32(&P->last_leaf); else l = fetch_i32(&P->first_leaf);
     // a corrupted exchange ends the climb instead of indexing out of range
     if (l < 0 || r > I || l > r) {
       atomicAdd(&meta[kMetaErr], 1);
@@ -363,10 +447,10 @@ hipError_t build_tree_links(int dim, int leaf_size, int64_t n, const BuildBuffer
   }
   if (e != hipSuccess) return e;
   if (dim == 3)
-    k_leaves<3><<<grid_n, 256, 0, s>>>(b.X, b.Y, b.Z, n, b.inode, b.meta, b.leaf_begin,
+    k_leaves<3><<<grid_n, kLeafBlock, 0, s>>>(b.X, b.Y, b.Z, n, b.inode, b.meta, b.leaf_begin,
                                       b.leaf_parent, b.leaf_of, b.root_box);
   else
-    k_leaves<2><<<grid_n, 256, 0, s>>>(b.X, b.Y, b.Z, n, b.inode, b.meta, b.leaf_begin,
+    k_leaves<2><<<grid_n, kLeafBlock, 0, s>>>(b.X, b.Y, b.Z, n, b.inode, b.meta, b.leaf_begin,
                                       b.leaf_parent, b.leaf_of, b.root_box);
   return hipGetLastError();
 }

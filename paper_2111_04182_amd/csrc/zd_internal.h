@@ -235,8 +235,12 @@ struct BuildBuffers {
   const int32_t *seg = nullptr;       // forest: cloud of each sorted position
   const int32_t *seg_leaf = nullptr;  // forest: leaf size of each cloud
 };
+// aos (nullable): also write each point as one (x, y, z, 0) / (x, y) record,
+// so that the later gather reads one aligned record per point instead of
+// one 8-byte value from each coordinate array
 hipError_t encode_keys(const Geometry &g, const double *xyz, int64_t stride, int64_t n,
-                       int32_t id_base, uint64_t *key, int32_t *id, hipStream_t s);
+                       int32_t id_base, uint64_t *key, int32_t *id, hipStream_t s,
+                       double *aos = nullptr);
 // Forest: per-cloud key geometry (seg_lo/seg_S [C][3]) and the cloud of
 // every point (seg [n]); offsets is a device copy of the cloud bounds.
 hipError_t forest_geometry(int dim, const double *xyz, int64_t n, const int64_t *offsets, int C,
@@ -245,9 +249,10 @@ hipError_t forest_geometry(int dim, const double *xyz, int64_t n, const int64_t 
 hipError_t encode_keys_seg(const Geometry &g, const double *xyz, int64_t n, const int32_t *seg,
                            const double *seg_lo, const double *seg_S, uint64_t *key, int32_t *id,
                            hipStream_t s);
+// aos (nullable): read the points from encode_keys' records instead of xyz
 hipError_t gather_points(int dim, const double *xyz, int64_t stride, const int32_t *id,
                          int64_t n, double *X, double *Y, double *Z, int32_t *slot_of,
-                         hipStream_t s);
+                         hipStream_t s, const double *aos = nullptr);
 hipError_t build_tree_links(int dim, int leaf_size, int64_t n, const BuildBuffers &b,
                             hipStream_t s);
 
