@@ -193,6 +193,16 @@ void destroy(zd_tree t) {
   delete t;
 }
 
+// One int32 from device memory, read on stream s through the thread's
+// pinned buffer (a pageable destination costs a staged copy).
+hipError_t read_i32(const int32_t *dptr, int32_t *out, hipStream_t s) {
+  int32_t *h = host_flag();
+  hipError_t e = hipMemcpyAsync(h ? h : out, dptr, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && h) *out = *h;
+  return e;
+}
+
 constexpr int64_t kMaxPoints = (int64_t)INT32_MAX - 1;
 
 }  // namespace
@@ -258,10 +268,13 @@ zd_status zd_build(const zd_params *p, const double *xyz, int64_t n, void *strea
       // the bounding cube of the data: one read-back
       double *d = nullptr;
       double h[6];
+      double *ph = reinterpret_cast<double *>(host_flag());  // 64 pinned bytes, or null
       e = dev_alloc_n(&d, 6, s);
       if (e == hipSuccess) e = box_reduce(dim, xyz, n, d, s);
-      if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(ph ? ph : h, d, sizeof(h), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e == hipSuccess && ph)
+        for (int c = 0; c < 6; ++c) h[c] = ph[c];
       dev_release(d, s);
       if (e == hipSuccess) {
         double side = 0.0;
@@ -343,9 +356,7 @@ zd_status zd_insert_batch(zd_tree t, const double *xyz, int64_t m, int32_t *out_
   int32_t bad = 0;
   if (e == hipSuccess) e = fill_i32(t->meta + kMetaErr, 0, 1, s);
   if (e == hipSuccess) e = count_outside_box(dim, xyz, m, t->geo.lo, t->hi, t->meta + kMetaErr, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(&bad, t->meta + kMetaErr, sizeof(bad), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = read_i32(t->meta + kMetaErr, &bad, s);
   if (e != hipSuccess) {
     t->broken = true;
     return to_status(e);
@@ -411,9 +422,7 @@ zd_status zd_delete_batch(zd_tree t, const int32_t *ids, int64_t m, void *stream
   if (e == hipSuccess) e = fill_i32(t->meta + kMetaErr, 0, 1, s);
   if (e == hipSuccess)
     e = validate_delete(ids, m, t->cap, t->slot_of, t->mark, t->meta + kMetaErr, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(&bad, t->meta + kMetaErr, sizeof(bad), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = read_i32(t->meta + kMetaErr, &bad, s);
   if (e == hipSuccess && bad) e = unmark_ids(ids, m, t->cap, t->mark, s);
   if (e != hipSuccess) {
     t->broken = true;
@@ -464,9 +473,7 @@ zd_status zd_info(zd_tree t, int64_t *n_live, int64_t *id_capacity, int64_t *n_l
   if (!t) return ZD_EINVAL;
   int32_t I = 0;
   if (t->st.n > 0) {
-    hipError_t e = hipMemcpyAsync(&I, t->meta + kMetaInternal, sizeof(I), hipMemcpyDeviceToHost,
-                                  t->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(t->stream);
+    hipError_t e = read_i32(t->meta + kMetaInternal, &I, t->stream);
     if (e != hipSuccess) return to_status(e);
   }
   if (n_live) *n_live = t->st.n;
@@ -493,8 +500,7 @@ zd_status zd_export(zd_tree t, uint64_t *keys, int32_t *ids, int64_t *leaf_count
   if (n == 0) return ZD_OK;
   hipStream_t s = t->stream;
   int32_t I = 0;
-  hipError_t e = hipMemcpyAsync(&I, t->meta + kMetaInternal, sizeof(I), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipError_t e = read_i32(t->meta + kMetaInternal, &I, s);
   if (e != hipSuccess) return to_status(e);
   const int64_t nl = (int64_t)I + 1;
   std::vector<int32_t> lb(nl + 1), lp(nl);

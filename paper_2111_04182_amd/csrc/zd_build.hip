@@ -208,11 +208,6 @@ hipError_t gather_points(int dim, const double *xyz, int64_t stride, const int32
 
 // ------------------------------------------------------------------ flags --
 
-// keys a and b agree on every bit above `bit`
-__device__ __forceinline__ bool same_prefix(uint64_t a, uint64_t b, int bit) {
-  return bit >= 63 ? true : ((a ^ b) >> (bit + 1)) == 0;
-}
-
 // Split bit between sorted positions i and i+1.  In a forest the order is by
 // (cloud, key): a change of cloud splits above every key bit, at 64 + the
 // highest differing bit of the cloud numbers, so the top of the tree
@@ -225,29 +220,39 @@ __device__ __forceinline__ int pos_split_bit(const uint64_t *key, const int32_t 
   return split_bit(key[i], key[i + 1]);
 }
 
-__global__ void k_split_flags(const uint64_t *__restrict__ key, const int32_t *__restrict__ seg,
+// Split bit of every adjacent pair (-1 for equal keys, >= 64 between two
+// clouds), one byte each: the flag pass scans these instead of keys.
+__global__ void k_split_bits(const uint64_t *__restrict__ key, const int32_t *__restrict__ seg,
+                             int64_t n, int8_t *__restrict__ sb) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
+  sb[i] = (int8_t)pos_split_bit(key, seg, i);
+}
+
+// Position i (between sorted points i and i+1) is an internal node iff the
+// run of points that share the prefix above its split bit b holds more than
+// L points (the leaf test of Algorithm 1).  Point x shares that prefix with
+// point i iff no split between them exceeds b, so the run extends from i
+// while the adjacent split bits stay <= b, and the scan stops once more than
+// L points are seen.
+__global__ void k_split_flags(const int8_t *__restrict__ sb, const int32_t *__restrict__ seg,
                               int64_t n, int L, const int32_t *__restrict__ seg_leaf,
                               int32_t *__restrict__ flag) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n - 1) return;
-  const int b = pos_split_bit(key, seg, i);
+  const int b = sb[i];
   int32_t f = 0;
   if (b >= 64) {
     f = 1;  // cloud boundaries are always internal: no leaf mixes clouds
   } else if (b >= 0) {
-    // points i and i+1 are on the two sides; extend each side while the keys
-    // keep the node's prefix (and cloud), stopping once more than L points
-    // are seen
-    const uint64_t ki = key[i];
-    const int32_t si = seg ? seg[i] : 0;
-    const int Li = seg_leaf ? seg_leaf[si] : L;
+    const int Li = seg_leaf ? seg_leaf[seg[i]] : L;
     int64_t left = 1, right = 1;
-    for (int64_t x = i - 1; x >= 0 && left + right <= Li; --x) {
-      if ((seg && seg[x] != si) || !same_prefix(key[x], ki, b)) break;
+    for (int64_t y = i - 1; y >= 0 && left + right <= Li; --y) {
+      if (sb[y] > b) break;
       ++left;
     }
-    for (int64_t x = i + 2; x < n && left + right <= Li; ++x) {
-      if ((seg && seg[x] != si) || !same_prefix(key[x], ki, b)) break;
+    for (int64_t y = i + 1; y < n - 1 && left + right <= Li; ++y) {
+      if (sb[y] > b) break;
       ++right;
     }
     f = (left + right > Li) ? 1 : 0;
@@ -258,13 +263,12 @@ __global__ void k_split_flags(const uint64_t *__restrict__ key, const int32_t *_
 // ---------------------------------------------------------------- compact --
 
 __global__ void k_compact(const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
-                          const uint64_t *__restrict__ key, const int32_t *__restrict__ seg,
-                          int64_t n, INode *__restrict__ inode) {
+                          const int8_t *__restrict__ sb, int64_t n, INode *__restrict__ inode) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n - 1 || !flag[i]) return;
   INode &N = inode[pos[i]];
   N.split = (int32_t)i;
-  N.bit = pos_split_bit(key, seg, i);
+  N.bit = sb[i];
   N.visits = 0;
   N.parent = -1;
 }
@@ -433,15 +437,24 @@ hipError_t build_tree_links(int dim, int leaf_size, int64_t n, const BuildBuffer
   }
   const unsigned grid_n = (unsigned)((n + 255) / 256);
   if (n > 1) {
-    k_split_flags<<<grid_n, 256, 0, s>>>(b.key, b.seg, n, leaf_size, b.seg_leaf, b.flag);
-    e = hipGetLastError();
+    int8_t *sb = nullptr;
+    e = dev_alloc_n(&sb, n, s);
+    if (e == hipSuccess) {
+      k_split_bits<<<grid_n, 256, 0, s>>>(b.key, b.seg, n, sb);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      k_split_flags<<<grid_n, 256, 0, s>>>(sb, b.seg, n, leaf_size, b.seg_leaf, b.flag);
+      e = hipGetLastError();
+    }
     // exclusive positions overwrite leaf_of (free until the leaf pass)
     if (e == hipSuccess)
       e = exclusive_scan_i32(b.flag, b.leaf_of, n - 1, b.meta + kMetaInternal, s);
     if (e == hipSuccess) {
-      k_compact<<<grid_n, 256, 0, s>>>(b.flag, b.leaf_of, b.key, b.seg, n, b.inode);
+      k_compact<<<grid_n, 256, 0, s>>>(b.flag, b.leaf_of, sb, n, b.inode);
       e = hipGetLastError();
     }
+    dev_release(sb, s);
   } else {
     e = fill_i32(b.meta + kMetaInternal, 0, 1, s);
   }

@@ -183,7 +183,8 @@ __device__ __forceinline__ bool cand_lt(double d, int32_t i, double e, int32_t j
 // host-side internals (implemented across the .hip files)
 // ---------------------------------------------------------------------------
 
-// device allocation ordered on a stream (pool-backed).  While an arena is
+// device allocation ordered on a stream (cached blocks reused on the same
+// stream).  While an arena is
 // active on the calling thread (graph capture), allocations are carved from
 // it instead and releases are no-ops, so a captured graph calls no
 // allocator.
@@ -195,6 +196,9 @@ struct Arena {
   size_t used;
 };
 void arena_activate(Arena *a);  // nullptr deactivates
+// a pinned 64-byte host buffer of the calling thread (nullptr if pinned
+// memory is unavailable): destination of device-to-host status words
+int32_t *host_flag();
 
 template <typename T>
 hipError_t dev_alloc_n(T **p, int64_t n, hipStream_t s) {

@@ -1,25 +1,65 @@
 // zd_scan.hip -- device memory, fills and the device-wide exclusive scan.
 #include "zd_internal.h"
 
+#include <cstdint>
 #include <mutex>
+#include <unordered_map>
+#include <vector>
 
 namespace zd {
 
 // ---------------------------------------------------------------------------
-// stream-ordered allocation from the device's default memory pool; the pool
-// keeps freed blocks (release threshold = max), so repeated builds and
-// queries do not return to the driver.
+// device memory: a caching allocator.  Released blocks are kept per device
+// and handed out again to a request on the same stream whose size is within
+// [need, need + need/4]; stream order then makes the reuse safe without
+// events.  This keeps the runtime's allocator out of repeated builds and
+// updates (its stream-ordered free costs about 0.2 ms per block here).
+// Cached bytes per device are capped; beyond the cap, and when an
+// allocation fails, cached blocks go back to the runtime (hipFree, which
+// waits for the device).
 // ---------------------------------------------------------------------------
 
-static std::once_flag g_pool_once[64];
+namespace {
 
-static void configure_pool(int dev) {
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-    uint64_t thr = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+struct Block {
+  void *p;
+  size_t bytes;
+  hipStream_t s;
+  uint64_t tick;
+};
+
+struct DevCache {
+  std::vector<Block> free;                   // released, reusable
+  std::unordered_map<void *, size_t> live;   // handed out -> capacity
+  size_t cached = 0;
+  uint64_t tick = 0;
+};
+
+constexpr int kMaxDev = 64;
+constexpr size_t kCacheCap = size_t(32) << 30;
+std::mutex g_mu;
+DevCache g_cache[kMaxDev];
+
+size_t round_bytes(size_t b) {
+  const size_t g = b <= (size_t(1) << 20) ? 256 : (size_t(1) << 20);
+  return (b + g - 1) / g * g;
+}
+
+// evict until the cache holds at most `keep` bytes (caller holds g_mu)
+void evict_locked(DevCache &c, size_t keep) {
+  while (c.cached > keep && !c.free.empty()) {
+    size_t oldest = 0;
+    for (size_t i = 1; i < c.free.size(); ++i)
+      if (c.free[i].tick < c.free[oldest].tick) oldest = i;
+    const Block b = c.free[oldest];
+    c.free[oldest] = c.free.back();
+    c.free.pop_back();
+    c.cached -= b.bytes;
+    (void)hipFree(b.p);
   }
 }
+
+}  // namespace
 
 static thread_local Arena *tl_arena = nullptr;
 
@@ -36,15 +76,67 @@ hipError_t dev_alloc(void **p, size_t bytes, hipStream_t s) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  if (dev >= 0 && dev < 64) std::call_once(g_pool_once[dev], configure_pool, dev);
-  return hipMallocAsync(p, bytes, s);
+  if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+  const size_t need = round_bytes(bytes);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevCache &c = g_cache[dev];
+    size_t best = SIZE_MAX;
+    for (size_t i = 0; i < c.free.size(); ++i) {
+      const Block &b = c.free[i];
+      if (b.s == s && b.bytes >= need && b.bytes <= need + need / 4 &&
+          (best == SIZE_MAX || b.bytes < c.free[best].bytes))
+        best = i;
+    }
+    if (best != SIZE_MAX) {
+      const Block b = c.free[best];
+      c.free[best] = c.free.back();
+      c.free.pop_back();
+      c.cached -= b.bytes;
+      c.live[b.p] = b.bytes;
+      *p = b.p;
+      return hipSuccess;
+    }
+  }
+  e = hipMalloc(p, need);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      evict_locked(g_cache[dev], 0);
+    }
+    e = hipMalloc(p, need);
+  }
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache[dev].live[*p] = need;
+  return hipSuccess;
 }
 
 void dev_release(void *p, hipStream_t s) {
   if (!p) return;
   if (tl_arena && (char *)p >= tl_arena->base && (char *)p < tl_arena->base + tl_arena->size)
     return;
-  (void)hipFreeAsync(p, s);
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int dev = 0; dev < kMaxDev; ++dev) {
+    DevCache &c = g_cache[dev];
+    auto it = c.live.find(p);
+    if (it == c.live.end()) continue;
+    const size_t bytes = it->second;
+    c.live.erase(it);
+    c.free.push_back(Block{p, bytes, s, c.tick++});
+    c.cached += bytes;
+    evict_locked(c, kCacheCap);
+    return;
+  }
+}
+
+int32_t *host_flag() {
+  // a small pinned buffer per host thread for device-to-host status words
+  static thread_local int32_t *buf = nullptr;
+  if (!buf && hipHostMalloc(reinterpret_cast<void **>(&buf), 64, hipHostMallocDefault) != hipSuccess)
+    buf = nullptr;
+  return buf;
 }
 
 // ---------------------------------------------------------------------------
