@@ -320,3 +320,30 @@ def test_config3_full_size_sampled():
         assert_same_rows((ids[sel], d2[sel]), o.knn_all(k, qids=rows), f"config3 10M k={k}")
         del ids, d2
     g.close()
+
+
+def test_streams_and_block_reuse():
+    """Trees built, queried, updated and freed on two streams in turn: the
+    library's cached device blocks are reused only on the stream that
+    released them, and a tree used on a second stream waits for its first."""
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    sets = [W.uniform(2000 + 700 * i, 3, 60 + i) for i in range(5)]
+    wants = [oracle.brute_knn(P, 8) for P in sets]
+    for rep in range(2):
+        for i, P in enumerate(sets):
+            s = sa if (i + rep) % 2 == 0 else sb
+            other = sb if s is sa else sa
+            with torch.cuda.stream(s):
+                xyz = dev(P)
+                t = zd.ZdTree(xyz, 16, stream=s)
+            # query on the other stream, then on the tree's own
+            with torch.cuda.stream(other):
+                got = t.knn(8, stream=other)
+            other.synchronize()
+            assert_same_rows(got, wants[i], f"set {i} rep {rep} other stream")
+            with torch.cuda.stream(s):
+                got = t.knn(8, stream=s)
+            s.synchronize()
+            assert_same_rows(got, wants[i], f"set {i} rep {rep} own stream")
+            t.close()
+    torch.cuda.synchronize()
