@@ -93,7 +93,7 @@ struct Heap {
   }
 };
 
-// For larger k the candidate set is a binary max-heap of the k best (d2, id)
+// For k > 20 the candidate set is a binary max-heap of the k best (d2, id)
 // per lane, kept in LDS (slot-major: slot s of lane l at [s * 64 + l], so a
 // lane's bank never depends on the slot it touches).  Replacing the root and
 // sifting down costs O(log k) instead of the O(k) register shift, and the
@@ -186,7 +186,6 @@ struct HeapFor {
     using type = LdsHeap<KK>;            \
     static constexpr bool lds = true;    \
   };
-ZD_LDS_HEAP(20)
 ZD_LDS_HEAP(24)
 ZD_LDS_HEAP(32)
 ZD_LDS_HEAP(40)
@@ -215,6 +214,13 @@ __device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_read
 // sorted positions scored on either side of a query group before its walk
 constexpr int64_t kPrescore = 32;
 
+// maximum of v over the wavefront (every lane gets it)
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
 // one staged candidate point (32 bytes: two 16-byte LDS reads)
 struct Cand {
   double x, y, z;
@@ -223,14 +229,15 @@ struct Cand {
 };
 
 // The per-lane state of one wavefront's shared search.
-template <int D, int K>
+template <int D, int K, bool kExt = false>
 struct WaveSearch {
   const TreeView &t;
   Cand *stage;                   // this wavefront's 64-entry LDS slice
   double px, py, pz;             // this lane's query
   int32_t self;                  // excluded id (-1 for external queries)
   bool valid;                    // lane holds a query
-  int32_t skip_lo, skip_hi;      // sorted positions already scored
+  int32_t skip_lo, skip_hi;      // sorted positions already scored (all lanes)
+  int32_t own_lo, own_n;         // external queries: this lane's scored leaf
   int64_t budget;                // walk bound (never reached on a valid tree)
   uint64_t key_ref;              // Morton key of the group's middle query (child order)
   typename HeapFor<K>::type h;
@@ -302,7 +309,14 @@ struct WaveSearch {
           if (jj >= cnt) break;
         }
         const Cand q = stage[jj];
-        h.offer(dist2<D>(px, py, pz, q.x, q.y, q.z), q.id);
+        const double dd = dist2<D>(px, py, pz, q.x, q.y, q.z);
+        if constexpr (kExt) {
+          // a point of the lane's own leaf was scored before the walk
+          const bool seen = (uint32_t)(c + jj - own_lo) < (uint32_t)own_n;
+          h.offer(seen ? INFINITY : dd, seen ? INT_MAX : q.id);
+        } else {
+          h.offer(dd, q.id);
+        }
       }
       __builtin_amdgcn_wave_barrier();
     }
@@ -406,8 +420,8 @@ constexpr int waves_per_block() {
   return HeapFor<K>::lds ? 1 : 4;
 }
 
-template <int D, int K>
-__device__ __forceinline__ void bind_lds(WaveSearch<D, K> &s, char *smem, int w) {
+template <int D, int K, bool E>
+__device__ __forceinline__ void bind_lds(WaveSearch<D, K, E> &s, char *smem, int w) {
   char *base = smem + (size_t)w * wave_lds_bytes<K>();
   s.stage = reinterpret_cast<Cand *>(base);
   if constexpr (HeapFor<K>::lds) {
@@ -488,7 +502,7 @@ __global__ void __launch_bounds__(256) k_knn_ext(TreeView t, const double *__res
   const int64_t last = min(g0 + 63, m - 1);
   const int64_t i = min(g0 + lane, last);
   const int32_t r = order[i];
-  WaveSearch<D, K> s(t, nullptr);
+  WaveSearch<D, K, true> s(t, nullptr);
   bind_lds(s, smem, w);
   s.valid = g0 + lane <= last;
   s.px = q[r];
@@ -514,6 +528,31 @@ __global__ void __launch_bounds__(256) k_knn_ext(TreeView t, const double *__res
       const int b0 = (int)((k0 >> bit) & 1), b1 = (int)((k1 >> bit) & 1);
       if (b0 != b1) break;
       node = uni(N->child[b0]);
+    }
+    // every lane first scores the leaf its own key leads to (the bit-based
+    // descent of Section 2, per lane), which gives each lane a k-th
+    // distance from its own neighbourhood before the shared walk; the walk
+    // skips those points for that lane
+    {
+      const uint64_t myk = qkey[i];
+      int32_t x = node;
+      for (int guard = 0; x >= 0 && guard < 66; ++guard) {
+        const INode *N = &t.inode[x];
+        const int bit = N->bit;
+        x = N->child[(int)((myk >> bit) & 1)];
+      }
+      // (x >= 0 here only on a corrupted tree: nothing is scored then)
+      const int32_t lb = x < 0 ? t.leaf_begin[~x] : 0, le = x < 0 ? t.leaf_begin[~x + 1] : 0;
+      s.own_lo = lb;
+      s.own_n = s.valid ? le - lb : 0;
+      const int rounds = wave_max(s.own_n);
+      for (int jj = 0; jj < rounds; ++jj) {
+        const bool in = jj < s.own_n;
+        const int64_t j = lb + (in ? jj : 0);
+        const double dd = dist2<D>(s.px, s.py, s.pz, t.X[j], t.Y[j], D == 3 ? t.Z[j] : 0.0);
+        const int32_t q = t.id[j];
+        s.h.offer(in ? dd : INFINITY, in ? q : INT_MAX);
+      }
     }
     s.run_from(node);
   }
