@@ -232,7 +232,7 @@ struct Cand {
 template <int D, int K, bool kExt = false>
 struct WaveSearch {
   const TreeView &t;
-  Cand *stage;                   // this wavefront's 64-entry LDS slice
+  Cand *stage;                   // this wavefront's 64-entry LDS slice (candidates)
   double px, py, pz;             // this lane's query
   int32_t self;                  // excluded id (-1 for external queries)
   bool valid;                    // lane holds a query
@@ -251,8 +251,9 @@ struct WaveSearch {
   // Every lane scores the sorted positions [a, b] (64 at a time through LDS)
   // and the walk then skips them.  `own` is this lane's own sorted position,
   // which enters as (+inf, INT_MAX) and so never precedes the k-th entry.
-  // (External query groups cover many more tree points than their 64
-  // queries, and measured slower with a prescored window.)
+  // (All-points groups only: an external query group covers many more tree
+  // points than its 64 queries and measured slower with a shared window;
+  // its lanes score their own leaves instead.)
   __device__ __forceinline__ void prescore(int64_t a, int64_t b, int64_t own) {
     const int lane = threadIdx.x & 63;
     for (int64_t c = a; c <= b; c += 64) {
@@ -281,8 +282,9 @@ struct WaveSearch {
   }
 
   // every lane scores every point of the leaf, except the sorted positions
-  // [skip_lo, skip_hi] already scored (they hold every lane's own point, so
-  // no self test is needed here)
+  // [skip_lo, skip_hi] already scored by all lanes (for all-points rows they
+  // hold every lane's own point, so no self test is needed here) and, for
+  // external queries, the lane's own leaf
   __device__ __forceinline__ void scan_leaf(int32_t leaf) {
     const int lane = threadIdx.x & 63;
     const int32_t b = uni(t.leaf_begin[leaf]), e = uni(t.leaf_begin[leaf + 1]);
@@ -325,9 +327,9 @@ struct WaveSearch {
   // searchDown (Algorithm 2) below internal node `top`, whose own box the
   // caller has already tested.  The walk is the same on every lane, so its
   // stack of pending (node, side) links is one VGPR holding entry i in lane
-  // i (a lane select to push, readlane to pop: no memory traffic).  Each step tests one child
-  // box with the current k-th distance; entering an internal node pushes its
-  // farther child and tests the nearer one first.  Split bits strictly
+  // i (a lane select to push, readlane to pop: no memory traffic).  Each
+  // step tests one child box with the current k-th distance; entering an
+  // internal node pushes its farther child and tests the nearer one first.  Split bits strictly
   // decrease downwards and lie in [0, 64) below a tree or cloud root, so a
   // path holds at most 64 internal nodes and the stack at most 64 entries;
   // a deeper stack only occurs on a corrupted tree and ends the walk, like
