@@ -19,7 +19,10 @@
  *     passed the call.
  *   - The caller owns every input and output buffer.  The library keeps its
  *     own copies of what it needs (the Morton-ordered points, the nodes, the
- *     id map) and frees them in zd_free.
+ *     id map) and releases them in zd_free.  Released device blocks stay in
+ *     the library's cache and are reused by later calls on the same stream;
+ *     the cache holds at most 32 GiB per device, and is handed back to the
+ *     runtime when an allocation fails (and at process exit).
  *   - Errors are returned before anything is enqueued; out-parameters are
  *     untouched on error.  No C++ exception crosses this interface.
  *   - Squared distances d2(a,b) = ((dx*dx + dy*dy) + dz*dz), dx = a.x - b.x,
