@@ -62,23 +62,71 @@ struct Heap {
   // The first test is one compare; a tie with the k-th distance falls through
   // to the exact (d2, id) comparisons, which then change nothing if the
   // candidate does not precede it.
+  template <bool kSplit = false>
   __device__ __forceinline__ void offer(double dd, int32_t q) {
     if (!(dd <= d[K - 1])) return;
+    if constexpr (kSplit && K >= 8) {
+      offer_split(dd, q);
+    } else {
+      bool lt[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) lt[j] = cand_lt(dd, q, d[j], id[j]);
+#pragma unroll
+      for (int j = K - 1; j > 0; --j) {
+        // slot j takes its left neighbour if the candidate precedes that
+        // neighbour, else the candidate if it precedes slot j, else stays
+        const double nd = lt[j - 1] ? d[j - 1] : (lt[j] ? dd : d[j]);
+        const int32_t ni = lt[j - 1] ? id[j - 1] : (lt[j] ? q : id[j]);
+        d[j] = nd;
+        id[j] = ni;
+      }
+      if (lt[0]) {
+        d[0] = dd;
+        id[0] = q;
+      }
+    }
+  }
+
+  // The same shift in two halves, for external queries and for the
+  // all-points walk at k >= 16, whose entries mostly arrive near the end of
+  // the sorted set: the upper half [H, K)
+  // always, taking slot H-1's old entry if the candidate precedes it; the
+  // lower half [0, H) only when some lane's candidate does.
+  __device__ __forceinline__ void offer_split(double dd, int32_t q) {
+    constexpr int H = K / 2;
     bool lt[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) lt[j] = cand_lt(dd, q, d[j], id[j]);
+    for (int j = H; j < K; ++j) lt[j] = cand_lt(dd, q, d[j], id[j]);
+    const bool low = cand_lt(dd, q, d[H - 1], id[H - 1]);
+    const double cd = d[H - 1];
+    const int32_t ci = id[H - 1];
 #pragma unroll
-    for (int j = K - 1; j > 0; --j) {
-      // slot j takes its left neighbour if the candidate precedes that
-      // neighbour, else the candidate if it precedes slot j, else stays
+    for (int j = K - 1; j > H; --j) {
       const double nd = lt[j - 1] ? d[j - 1] : (lt[j] ? dd : d[j]);
       const int32_t ni = lt[j - 1] ? id[j - 1] : (lt[j] ? q : id[j]);
       d[j] = nd;
       id[j] = ni;
     }
-    if (lt[0]) {
-      d[0] = dd;
-      id[0] = q;
+    {
+      const double nd = low ? cd : (lt[H] ? dd : d[H]);
+      const int32_t ni = low ? ci : (lt[H] ? q : id[H]);
+      d[H] = nd;
+      id[H] = ni;
+    }
+    if (__ballot(low) != 0) {
+#pragma unroll
+      for (int j = 0; j < H; ++j) lt[j] = cand_lt(dd, q, d[j], id[j]);
+#pragma unroll
+      for (int j = H - 1; j > 0; --j) {
+        const double nd = lt[j - 1] ? d[j - 1] : (lt[j] ? dd : d[j]);
+        const int32_t ni = lt[j - 1] ? id[j - 1] : (lt[j] ? q : id[j]);
+        d[j] = nd;
+        id[j] = ni;
+      }
+      if (lt[0]) {
+        d[0] = dd;
+        id[0] = q;
+      }
     }
   }
 
@@ -153,6 +201,7 @@ struct LdsHeap {
     hi[i * 64 + lane] = q;
   }
 
+  template <bool = false>
   __device__ __forceinline__ void offer(double dd, int32_t q) {
     if (!(dd <= root_d)) return;
     if (!cand_lt(dd, q, root_d, root_i)) return;
@@ -315,9 +364,10 @@ struct WaveSearch {
         if constexpr (kExt) {
           // a point of the lane's own leaf was scored before the walk
           const bool seen = (uint32_t)(c + jj - own_lo) < (uint32_t)own_n;
-          h.offer(seen ? INFINITY : dd, seen ? INT_MAX : q.id);
+          h.template offer<true>(seen ? INFINITY : dd, seen ? INT_MAX : q.id);
         } else {
-          h.offer(dd, q.id);
+          // (the split shift pays off in the walk for k >= 16)
+          h.template offer<(K >= 16)>(dd, q.id);
         }
       }
       __builtin_amdgcn_wave_barrier();
@@ -553,7 +603,7 @@ __global__ void __launch_bounds__(256) k_knn_ext(TreeView t, const double *__res
         const int64_t j = lb + (in ? jj : 0);
         const double dd = dist2<D>(s.px, s.py, s.pz, t.X[j], t.Y[j], D == 3 ? t.Z[j] : 0.0);
         const int32_t q = t.id[j];
-        s.h.offer(in ? dd : INFINITY, in ? q : INT_MAX);
+        s.h.template offer<true>(in ? dd : INFINITY, in ? q : INT_MAX);
       }
     }
     s.run_from(node);
