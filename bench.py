@@ -142,11 +142,11 @@ def main():
     ap.add_argument("--workload", default="uniform3d",
                     choices=["uniform3d", "spheres", "forest", "grad"])
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
+                    help="also run one elementwise pass over a 1 GiB tensor (reads and writes "
+                         "1 GiB: the reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design note, not part of this build)",
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
 
