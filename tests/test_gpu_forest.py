@@ -146,3 +146,31 @@ def test_forest_argument_errors():
             zd.ZdForest(xyz, bad)
     with pytest.raises(zd.ZdError):
         zd.ZdForest(xyz, off, leaf_sizes=np.zeros(len(off) - 1, dtype=np.int32))
+
+
+@pytest.mark.timeout(900)
+def test_forest_config4_full_size_sampled():
+    """The full batched workload (4096 clouds, 62M points, k=16) as the bench
+    runs it (captured plan, per-bucket leaf sizes): sampled rows of sampled
+    clouds against the oracle's brute force over that cloud."""
+    P, off = W.cfg4_forest()
+    xyz = dev(P)
+    k = 16
+    sizes = np.diff(off)
+    buckets = np.floor(np.log2(np.maximum(sizes, 1))).astype(np.int64)
+    ls = np.where(buckets < 10, 24, 32).astype(np.int32)
+    plan = zd.ZdForestPlan(xyz, off, k, leaf_sizes=ls)
+    ids, d2 = plan.run()
+    torch.cuda.synchronize()
+    gi_all, gd_all = ids, d2
+    rng = np.random.default_rng(11)
+    for c in rng.choice(len(off) - 1, 12, replace=False):
+        a, b = int(off[c]), int(off[c + 1])
+        rows = rng.choice(b - a, min(40, b - a), replace=False)
+        wi, wd = oracle.brute_knn(P[a:b], k, qids=rows)
+        sel = torch.from_numpy(a + rows).cuda()
+        gi = gi_all[sel].cpu().numpy()
+        gd = gd_all[sel].cpu().numpy()
+        assert np.array_equal(gi, np.where(wi >= 0, wi + a, -1)), f"cloud {c} ids"
+        assert np.array_equal(gd, wd), f"cloud {c} d2"
+    plan.close()
