@@ -327,9 +327,9 @@ def bench_forest(args):
     P, off = W.cfg4_forest()
     N = P.shape[0]
     xyz = zd.soa(torch.from_numpy(P))
-    log(f"bench forest: N={N}, autotuning leaf sizes")
-    ls, rep = tune_forest(xyz, off, k, reps=1, log=log)
-    plan = zd.ZdForestPlan(xyz, off, k, leaf_sizes=ls)
+    log(f"bench forest: N={N}, autotuning leaf sizes and launch shape")
+    ls, waves, rep = tune_forest(xyz, off, k, reps=1, log=log)
+    plan = zd.ZdForestPlan(xyz, off, k, leaf_sizes=ls, query_waves=waves)
     plan.run()
     torch.cuda.synchronize()
     ms_forest, _ = _events(plan.run, max(3, args.steps))
@@ -347,7 +347,7 @@ def bench_forest(args):
 
     def per_cloud():
         for a, b, cx, box, L in clouds:
-            t = zd.ZdTree(cx, L, box=box)
+            t = zd.ZdTree(cx, L, box=box, query_waves=waves)
             zd.zd_knn(t.handle, None, b - a, k, ids_pc[a:b], d2_pc[a:b])
             t.close()
 
@@ -367,7 +367,8 @@ def bench_forest(args):
                                                     "log-uniform 1000-65536, k=16", "N": N},
         "forest_graph_ms": ms_forest, "per_cloud_calls_ms": ms_pc,
         "speedup_vs_per_cloud": ms_pc / ms_forest, "rows_match_per_cloud": ok,
-        "leaf_size_by_bucket": rep.get("choice"), "autotune_best_ms": rep.get("best_ms")}),
+        "leaf_size_by_bucket": rep.get("choice"), "query_waves": waves,
+        "autotune_best_ms": rep.get("best_ms")}),
         flush=True)
 
 

@@ -75,7 +75,14 @@ typedef enum {
  *               the largest extent, 1 if all points coincide).  Rounding to
  *               integers (Section 3.1) maps [lo, hi] onto 2^(B-1) cells per
  *               coordinate: cell = clamp(floor((x - lo) * S), 0, 2^(B-1)-1),
- *               S = 2^(B-1) / (hi - lo). */
+ *               S = 2^(B-1) / (hi - lo).
+ *   query_waves: launch shape of this tree's k-NN queries: wavefronts per
+ *               workgroup, 1, 2 or 4 (0 means 1).  Each wavefront answers 64
+ *               queries whatever the value; it changes only how wavefronts are
+ *               packed into workgroups, never the rows.  For k > 20 (per-lane
+ *               candidate sets in LDS) the value is lowered, if needed, until
+ *               the workgroup's LDS fits in one CU.  Not in the paper: a tuning
+ *               knob of this implementation. */
 typedef struct {
   int32_t dim;
   int32_t leaf_size;
@@ -83,6 +90,7 @@ typedef struct {
   const uint64_t *shift;
   const double *box_lo;
   const double *box_hi;
+  int32_t query_waves;
 } zd_params;
 
 /* Build a zd-tree over n points (Section 2, "Construction", Algorithm 1).
@@ -92,8 +100,8 @@ typedef struct {
  * synchronises `stream` once to read the data's bounding cube.
  * Errors: ZD_EINVAL for a NULL params/out, dim not 2 or 3, leaf_size < 1,
  * n < 0, n > 2^31 - 2, a NULL xyz with n > 0, n == 0 without a box, only one
- * of box_lo / box_hi given, hi <= lo, a non-finite box, or a shift value out
- * of range; ZD_ENOMEM; ZD_EDEVICE. */
+ * of box_lo / box_hi given, hi <= lo, a non-finite box, a shift value out
+ * of range, or query_waves not 0, 1, 2 or 4; ZD_ENOMEM; ZD_EDEVICE. */
 ZD_API zd_status zd_build(const zd_params *params, const double *xyz, int64_t n,
                    void *stream, zd_tree *out);
 

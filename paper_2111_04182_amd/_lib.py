@@ -34,7 +34,8 @@ class ZdError(RuntimeError):
 
 class _Params(C.Structure):
     _fields_ = [("dim", C.c_int32), ("leaf_size", C.c_int32), ("shift_seed", C.c_uint64),
-                ("shift", C.c_void_p), ("box_lo", C.c_void_p), ("box_hi", C.c_void_p)]
+                ("shift", C.c_void_p), ("box_lo", C.c_void_p), ("box_hi", C.c_void_p),
+                ("query_waves", C.c_int32)]
 
 
 _lib = None
@@ -119,7 +120,7 @@ def _check_soa(xyz: torch.Tensor, dim: int | None = None):
 # --------------------------------------------------------------------------
 
 def zd_build(xyz: torch.Tensor, leaf_size: int = 16, box=None, shift_seed: int = 0,
-             shift=None, stream=None) -> C.c_void_p:
+             shift=None, stream=None, query_waves: int = 0) -> C.c_void_p:
     """Build a tree over SoA points xyz (d, n); returns the handle."""
     _check_soa(xyz)
     dim, n = xyz.shape
@@ -133,7 +134,8 @@ def zd_build(xyz: torch.Tensor, leaf_size: int = 16, box=None, shift_seed: int =
         sh = np.ascontiguousarray(shift, dtype=np.uint64)
         if sh.shape != (dim,):
             raise ValueError("shift must have d entries")
-    p = _Params(dim, leaf_size, shift_seed & 0xFFFFFFFFFFFFFFFF, _hptr(sh), _hptr(lo), _hptr(hi))
+    p = _Params(dim, leaf_size, shift_seed & 0xFFFFFFFFFFFFFFFF, _hptr(sh), _hptr(lo), _hptr(hi),
+                query_waves)
     out = C.c_void_p()
     _check(lib().zd_build(C.byref(p), _dptr(xyz), n, _stream(stream), C.byref(out)), "zd_build")
     return out
@@ -215,10 +217,10 @@ class ZdTree:
     """A zd-tree on the current GPU (owns one libzd handle)."""
 
     def __init__(self, xyz: torch.Tensor, leaf_size: int = 16, box=None, shift_seed: int = 0,
-                 shift=None, stream=None):
+                 shift=None, stream=None, query_waves: int = 0):
         self.dim = xyz.shape[0]
         self.leaf_size = leaf_size
-        self._h = zd_build(xyz, leaf_size, box, shift_seed, shift, stream)
+        self._h = zd_build(xyz, leaf_size, box, shift_seed, shift, stream, query_waves)
         self.cap = xyz.shape[1]  # id capacity, tracked here to avoid a sync
 
     @property
@@ -265,7 +267,7 @@ class ZdTree:
 # batched forest
 # --------------------------------------------------------------------------
 
-def _forest_args(xyz, offsets, leaf_size, leaf_sizes, box, shift_seed, shift):
+def _forest_args(xyz, offsets, leaf_size, leaf_sizes, box, shift_seed, shift, query_waves):
     _check_soa(xyz)
     dim, n = xyz.shape
     off = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -276,14 +278,15 @@ def _forest_args(xyz, offsets, leaf_size, leaf_sizes, box, shift_seed, shift):
         hi = np.ascontiguousarray(box[1], dtype=np.float64)
     if shift is not None:
         sh = np.ascontiguousarray(shift, dtype=np.uint64)
-    p = _Params(dim, leaf_size, shift_seed & 0xFFFFFFFFFFFFFFFF, _hptr(sh), _hptr(lo), _hptr(hi))
+    p = _Params(dim, leaf_size, shift_seed & 0xFFFFFFFFFFFFFFFF, _hptr(sh), _hptr(lo), _hptr(hi),
+                query_waves)
     return p, dim, n, off, ls, (lo, hi, sh)
 
 
 def zd_forest_build(xyz, offsets, leaf_size=16, leaf_sizes=None, box=None, shift_seed=0,
-                    shift=None, stream=None):
+                    shift=None, stream=None, query_waves=0):
     p, dim, n, off, ls, keep = _forest_args(xyz, offsets, leaf_size, leaf_sizes, box,
-                                            shift_seed, shift)
+                                            shift_seed, shift, query_waves)
     out = C.c_void_p()
     _check(lib().zd_forest_build(C.byref(p), _dptr(xyz), n, _hptr(off), len(off) - 1, _hptr(ls),
                                  _stream(stream), C.byref(out)), "zd_forest_build")
@@ -296,9 +299,9 @@ def zd_forest_knn(forest, k, out_ids, out_d2, stream=None):
 
 
 def zd_forest_plan(xyz, offsets, k, out_ids, out_d2, leaf_size=16, leaf_sizes=None, box=None,
-                   shift_seed=0, shift=None, stream=None):
+                   shift_seed=0, shift=None, stream=None, query_waves=0):
     p, dim, n, off, ls, keep = _forest_args(xyz, offsets, leaf_size, leaf_sizes, box,
-                                            shift_seed, shift)
+                                            shift_seed, shift, query_waves)
     out = C.c_void_p()
     _check(lib().zd_forest_plan(C.byref(p), _dptr(xyz), n, _hptr(off), len(off) - 1, _hptr(ls),
                                 k, _dptr(out_ids), _dptr(out_d2), _stream(stream), C.byref(out)),
@@ -320,11 +323,11 @@ class ZdForest:
     offsets[c]..offsets[c+1] of the SoA tensor xyz)."""
 
     def __init__(self, xyz, offsets, leaf_size=16, leaf_sizes=None, box=None, shift_seed=0,
-                 shift=None, stream=None):
+                 shift=None, stream=None, query_waves=0):
         self.n = xyz.shape[1]
         self._xyz = xyz
         self._h = zd_forest_build(xyz, offsets, leaf_size, leaf_sizes, box, shift_seed, shift,
-                                  stream)
+                                  stream, query_waves)
 
     def knn(self, k, stream=None):
         ids = torch.empty((self.n, k), dtype=torch.int32, device="cuda")
@@ -349,13 +352,13 @@ class ZdForestPlan:
     replays it on the current contents of xyz, filling self.ids / self.d2."""
 
     def __init__(self, xyz, offsets, k, leaf_size=16, leaf_sizes=None, box=None, shift_seed=0,
-                 shift=None, stream=None):
+                 shift=None, stream=None, query_waves=0):
         n = xyz.shape[1]
         self._xyz = xyz
         self.ids = torch.empty((n, k), dtype=torch.int32, device="cuda")
         self.d2 = torch.empty((n, k), dtype=torch.float64, device="cuda")
         self._h = zd_forest_plan(xyz, offsets, k, self.ids, self.d2, leaf_size, leaf_sizes, box,
-                                 shift_seed, shift, stream)
+                                 shift_seed, shift, stream, query_waves)
 
     def run(self, stream=None):
         zd_forest_run(self._h, stream)

@@ -71,6 +71,7 @@ zd_status to_status(hipError_t e) {
 
 struct zd_tree_s {
   int dim = 0, L = 0;
+  int qwaves = 1;  // wavefronts per workgroup of the query launches
   Geometry geo{};
   double hi[3] = {0, 0, 0};
   int64_t cap = 0;   // id capacity
@@ -176,6 +177,8 @@ hipError_t grow_ids(zd_tree t, int64_t need) {
   return hipSuccess;
 }
 
+bool valid_query_waves(int32_t w) { return w == 0 || w == 1 || w == 2 || w == 4; }
+
 bool finite3(const double *v, int dim) {
   for (int c = 0; c < dim; ++c)
     if (!std::isfinite(v[c])) return false;
@@ -227,6 +230,7 @@ zd_status zd_build(const zd_params *p, const double *xyz, int64_t n, void *strea
   if (!p || !out) return ZD_EINVAL;
   const int dim = p->dim;
   if ((dim != 2 && dim != 3) || p->leaf_size < 1 || n < 0 || n > kMaxPoints) return ZD_EINVAL;
+  if (!valid_query_waves(p->query_waves)) return ZD_EINVAL;
   if (n > 0 && !xyz) return ZD_EINVAL;
   if ((p->box_lo == nullptr) != (p->box_hi == nullptr)) return ZD_EINVAL;
   if (n == 0 && !p->box_lo) return ZD_EINVAL;
@@ -246,6 +250,7 @@ zd_status zd_build(const zd_params *p, const double *xyz, int64_t n, void *strea
   t->stream = s;
   t->dim = dim;
   t->L = p->leaf_size;
+  t->qwaves = p->query_waves ? p->query_waves : 1;
   t->geo.dim = dim;
   t->geo.B = B;
   for (int c = 0; c < dim; ++c)
@@ -331,9 +336,10 @@ zd_status zd_knn(zd_tree t, const double *q_xyz, int64_t m, int32_t k, int32_t *
   if (e == hipSuccess && m > 0) {
     if (!q_xyz) {
       if (t->cap > t->st.n) e = fill_dead_rows(t->slot_of, t->cap, k, out_ids, out_d2, s);
-      if (e == hipSuccess) e = knn_all_points(t->dim, t->view(), k, out_ids, out_d2, s);
+      if (e == hipSuccess)
+        e = knn_all_points(t->dim, t->view(), k, out_ids, out_d2, s, t->qwaves);
     } else {
-      e = knn_external(t->dim, t->view(), t->geo, q_xyz, m, k, out_ids, out_d2, s);
+      e = knn_external(t->dim, t->view(), t->geo, q_xyz, m, k, out_ids, out_d2, s, t->qwaves);
     }
   }
   if (e != hipSuccess) {
@@ -610,6 +616,7 @@ zd_status forest_setup(const zd_params *p, const double *xyz, int64_t n, const i
   if (!p || !out || !offsets || C < 1) return ZD_EINVAL;
   const int dim = p->dim;
   if ((dim != 2 && dim != 3) || p->leaf_size < 1 || n < 0 || n > kMaxPoints) return ZD_EINVAL;
+  if (!valid_query_waves(p->query_waves)) return ZD_EINVAL;
   if (n > 0 && !xyz) return ZD_EINVAL;
   if ((p->box_lo == nullptr) != (p->box_hi == nullptr)) return ZD_EINVAL;
   if (offsets[0] != 0 || offsets[C] != n) return ZD_EINVAL;
@@ -641,6 +648,7 @@ zd_status forest_setup(const zd_params *p, const double *xyz, int64_t n, const i
   t->stream = s;
   t->dim = dim;
   t->L = p->leaf_size;
+  t->qwaves = p->query_waves ? p->query_waves : 1;
   t->geo.dim = dim;
   t->geo.B = B;
   for (int c = 0; c < dim; ++c)
@@ -756,7 +764,8 @@ zd_status zd_forest_knn(zd_forest f, int32_t k, int32_t *out_ids, double *out_d2
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = bind_stream(f->t, s);
   if (e == hipSuccess)
-    e = knn_all_points(f->t->dim, f->t->view(), k, out_ids, out_d2, s, f->groups, f->ngroups);
+    e = knn_all_points(f->t->dim, f->t->view(), k, out_ids, out_d2, s, f->t->qwaves, f->groups,
+                       f->ngroups);
   return to_status(e);
 }
 
@@ -782,8 +791,8 @@ zd_status zd_forest_plan(const zd_params *params, const double *xyz, int64_t n,
     arena_activate(&f->arena);
     hipError_t e1 = forest_build_pass(f, f->cap);
     if (e1 == hipSuccess)
-      e1 = knn_all_points(f->t->dim, f->t->view(), k, out_ids, out_d2, f->cap, f->groups,
-                          f->ngroups);
+      e1 = knn_all_points(f->t->dim, f->t->view(), k, out_ids, out_d2, f->cap, f->t->qwaves,
+                          f->groups, f->ngroups);
     arena_activate(nullptr);
     hipError_t e2 = hipStreamEndCapture(f->cap, &f->graph);
     e = e1 != hipSuccess ? e1 : e2;

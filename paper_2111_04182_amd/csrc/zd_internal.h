@@ -263,11 +263,13 @@ hipError_t build_tree_links(int dim, int leaf_size, int64_t n, const BuildBuffer
 // Queries.  groups == nullptr: wavefront w answers sorted positions
 // [64w, 64w + 64); otherwise wavefront w answers [groups[w].x, groups[w].y],
 // which lie in the cloud [groups[w].z, groups[w].w] (a forest's groups never
-// span two clouds).
+// span two clouds).  query_waves: wavefronts per workgroup (1, 2 or 4).
 hipError_t knn_all_points(int dim, const TreeView &t, int k, int32_t *out_ids, double *out_d2,
-                          hipStream_t s, const int4 *groups = nullptr, int64_t ngroups = 0);
+                          hipStream_t s, int query_waves, const int4 *groups = nullptr,
+                          int64_t ngroups = 0);
 hipError_t knn_external(int dim, const TreeView &t, const Geometry &g, const double *q,
-                        int64_t m, int k, int32_t *out_ids, double *out_d2, hipStream_t s);
+                        int64_t m, int k, int32_t *out_ids, double *out_d2, hipStream_t s,
+                        int query_waves);
 hipError_t fill_dead_rows(const int32_t *slot_of, int64_t cap, int k, int32_t *out_ids,
                           double *out_d2, hipStream_t s);
 

@@ -7,25 +7,26 @@
 namespace zd {
 
 hipError_t knn_all_d2(const TreeView &t, int k, int32_t *ids, double *d2, hipStream_t s,
-                      const int4 *groups, int64_t ngroups);
+                      const int4 *groups, int64_t ngroups, int query_waves);
 hipError_t knn_all_d3(const TreeView &t, int k, int32_t *ids, double *d2, hipStream_t s,
-                      const int4 *groups, int64_t ngroups);
+                      const int4 *groups, int64_t ngroups, int query_waves);
 hipError_t knn_ext_d2(const TreeView &t, const double *q, const uint64_t *qkey,
                       const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
-                      hipStream_t s);
+                      hipStream_t s, int query_waves);
 hipError_t knn_ext_d3(const TreeView &t, const double *q, const uint64_t *qkey,
                       const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
-                      hipStream_t s);
+                      hipStream_t s, int query_waves);
 
 hipError_t knn_all_points(int dim, const TreeView &t, int k, int32_t *out_ids, double *out_d2,
-                          hipStream_t s, const int4 *groups, int64_t ngroups) {
+                          hipStream_t s, int query_waves, const int4 *groups, int64_t ngroups) {
   if (t.n <= 0 || (groups && ngroups <= 0)) return hipSuccess;
-  return dim == 3 ? knn_all_d3(t, k, out_ids, out_d2, s, groups, ngroups)
-                  : knn_all_d2(t, k, out_ids, out_d2, s, groups, ngroups);
+  return dim == 3 ? knn_all_d3(t, k, out_ids, out_d2, s, groups, ngroups, query_waves)
+                  : knn_all_d2(t, k, out_ids, out_d2, s, groups, ngroups, query_waves);
 }
 
 hipError_t knn_external(int dim, const TreeView &t, const Geometry &g, const double *q,
-                        int64_t m, int k, int32_t *out_ids, double *out_d2, hipStream_t s) {
+                        int64_t m, int k, int32_t *out_ids, double *out_d2, hipStream_t s,
+                        int query_waves) {
   if (m <= 0) return hipSuccess;
   // sort the queries by their Morton keys so a wavefront's 64 queries are
   // neighbours in space; rows are still written in query order
@@ -38,8 +39,8 @@ hipError_t knn_external(int dim, const TreeView &t, const Geometry &g, const dou
   if (e == hipSuccess) e = encode_keys(g, q, m, m, 0, key, order, s);
   if (e == hipSuccess) e = radix_sort_pairs(key, order, key_tmp, order_tmp, m, dim * g.B, s);
   if (e == hipSuccess)
-    e = dim == 3 ? knn_ext_d3(t, q, key, order, m, k, out_ids, out_d2, s)
-                 : knn_ext_d2(t, q, key, order, m, k, out_ids, out_d2, s);
+    e = dim == 3 ? knn_ext_d3(t, q, key, order, m, k, out_ids, out_d2, s, query_waves)
+                 : knn_ext_d2(t, q, key, order, m, k, out_ids, out_d2, s, query_waves);
   dev_release(key, s);
   dev_release(order, s);
   dev_release(key_tmp, s);

@@ -5,10 +5,10 @@ namespace zd {
 
 hipError_t knn_ext_d3(const TreeView &t, const double *q, const uint64_t *qkey,
                       const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
-                      hipStream_t s) {
+                      hipStream_t s, int query_waves) {
   switch (k_bucket(k)) {
 #define X(KK) \
-  case KK: return launch_knn_ext<3, KK>(t, q, qkey, order, m, k, ids, d2, s);
+  case KK: return launch_knn_ext<3, KK>(t, q, qkey, order, m, k, ids, d2, s, query_waves);
     ZD_FOR_EACH_K(X)
 #undef X
   }

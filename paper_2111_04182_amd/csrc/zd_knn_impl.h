@@ -467,9 +467,14 @@ template <int K>
 constexpr size_t wave_lds_bytes() {
   return 64 * sizeof(Cand) + (HeapFor<K>::lds ? (size_t)K * 64 * (sizeof(double) + sizeof(int32_t)) : 0);
 }
+// Wavefronts per workgroup of a query launch: the requested 1, 2 or 4,
+// halved while the workgroup's LDS would exceed one CU's 160 KiB (only the
+// k > 20 buckets, whose candidate sets live in LDS, come near it).
 template <int K>
-constexpr int waves_per_block() {
-  return HeapFor<K>::lds ? 1 : 4;
+int fit_waves(int want) {
+  int w = want == 2 || want == 4 ? want : 1;
+  while (w > 1 && (size_t)w * wave_lds_bytes<K>() > 160 * 1024) w >>= 1;
+  return w;
 }
 
 template <int D, int K, bool E>
@@ -489,7 +494,7 @@ __global__ void __launch_bounds__(256) k_knn_all(TreeView t, int k, int32_t *__r
   extern __shared__ __align__(16) char smem[];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int64_t gw = (int64_t)xcd_block(blockIdx.x, gridDim.x) * waves_per_block<K>() + w;
+  const int64_t gw = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + w;
   int64_t g0, last, c_lo, c_hi;  // the group, and the cloud that holds it
   if (groups) {
     if (gw >= ngroups) return;
@@ -549,7 +554,7 @@ __global__ void __launch_bounds__(256) k_knn_ext(TreeView t, const double *__res
   extern __shared__ __align__(16) char smem[];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int64_t g0 = ((int64_t)blockIdx.x * waves_per_block<K>() + w) * 64;
+  const int64_t g0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + w) * 64;
   if (g0 >= m) return;
   const int64_t last = min(g0 + 63, m - 1);
   const int64_t i = min(g0 + lane, last);
@@ -613,9 +618,9 @@ __global__ void __launch_bounds__(256) k_knn_ext(TreeView t, const double *__res
 
 template <int D, int K>
 hipError_t launch_knn_all(const TreeView &t, int k, int32_t *ids, double *d2, hipStream_t s,
-                          const int4 *groups, int64_t ngroups) {
+                          const int4 *groups, int64_t ngroups, int query_waves) {
   const int64_t waves = groups ? ngroups : (t.n + 63) / 64;
-  constexpr int wpb = waves_per_block<K>();
+  const int wpb = fit_waves<K>(query_waves);
   k_knn_all<D, K><<<(unsigned)((waves + wpb - 1) / wpb), 64 * wpb, wpb * wave_lds_bytes<K>(), s>>>(
       t, k, ids, d2, groups, ngroups);
   return hipGetLastError();
@@ -624,9 +629,9 @@ hipError_t launch_knn_all(const TreeView &t, int k, int32_t *ids, double *d2, hi
 template <int D, int K>
 hipError_t launch_knn_ext(const TreeView &t, const double *q, const uint64_t *qkey,
                           const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
-                          hipStream_t s) {
+                          hipStream_t s, int query_waves) {
   const int64_t waves = (m + 63) / 64;
-  constexpr int wpb = waves_per_block<K>();
+  const int wpb = fit_waves<K>(query_waves);
   k_knn_ext<D, K><<<(unsigned)((waves + wpb - 1) / wpb), 64 * wpb, wpb * wave_lds_bytes<K>(), s>>>(
       t, q, qkey, order, m, k, ids, d2);
   return hipGetLastError();

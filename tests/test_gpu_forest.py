@@ -77,6 +77,20 @@ def test_forest_per_cloud_leaf_sizes_do_not_change_rows():
         f.close()
 
 
+@pytest.mark.parametrize("waves", [2, 4])
+def test_forest_query_waves_do_not_change_rows(waves):
+    P, off = mixed_clouds(25)
+    want = oracle_rows(P, off, 16)
+    f = zd.ZdForest(dev(P), off, leaf_size=12, query_waves=waves)
+    same(f.knn(16), want, f"forest waves={waves}")
+    f.close()
+    plan = zd.ZdForestPlan(dev(P), off, 16, leaf_size=12, query_waves=waves)
+    ids, d2 = plan.run()
+    torch.cuda.synchronize()
+    same((ids, d2), want, f"forest plan waves={waves}")
+    plan.close()
+
+
 def test_forest_with_declared_box():
     P, off = mixed_clouds(22)
     P = (P - P.min(axis=0)) / (P.max(axis=0) - P.min(axis=0) + 1e-9)

@@ -108,6 +108,20 @@ def test_leaf_size_does_not_change_rows(L):
     g.close()
 
 
+@pytest.mark.parametrize("waves", [2, 4])
+@pytest.mark.parametrize("k", [10, 20, 50, 64])
+def test_query_waves_do_not_change_rows(waves, k):
+    # 6,037 points = 95 wavefronts and 1,013 queries = 16 wavefronts: the last
+    # workgroup of each launch is partly empty
+    P = W.clustered_small(6037, 3, 12)
+    Q = W.uniform(1013, 3, 13)
+    g = zd.ZdTree(dev(P), leaf_size=16, shift_seed=4, query_waves=waves)
+    assert_same_rows(g.knn(k), oracle.brute_knn(P, k), f"waves={waves} k={k}")
+    assert_same_rows(g.knn(k, dev(Q)), oracle.brute_knn(P, k, queries=Q),
+                     f"waves={waves} ext k={k}")
+    g.close()
+
+
 def test_config1_uniform2d_full():
     P = W.cfg1_uniform2d()
     g = zd.ZdTree(dev(P), leaf_size=16, box=W.UNIT2, shift_seed=0)
@@ -209,6 +223,9 @@ def test_invalid_arguments():
         zd.ZdTree(P, leaf_size=0)
     with pytest.raises(zd.ZdError):
         zd.ZdTree(P, box=(np.zeros(3), np.array([1.0, 0.0, 1.0])))
+    for w in (-1, 3, 8):
+        with pytest.raises(zd.ZdError):
+            zd.ZdTree(P, query_waves=w)
     g = zd.ZdTree(P, 4)
     with pytest.raises(zd.ZdError) as e:
         g.knn(65)

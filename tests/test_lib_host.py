@@ -48,6 +48,9 @@ def test_argument_errors_need_no_device(L):
     for dim, leaf, n in ((4, 16, 10), (1, 16, 10), (3, 0, 10), (3, 16, -1), (2, 16, 2**31)):
         p = B._Params(dim, leaf, 0, None, None, None)
         assert L.zd_build(C.byref(p), vp(1), n, None, C.byref(out)) == B.ZD_EINVAL
+    for w in (-1, 3, 5, 8):  # query_waves must be 0, 1, 2 or 4
+        p = B._Params(3, 16, 0, None, None, None, w)
+        assert L.zd_build(C.byref(p), vp(1), 10, None, C.byref(out)) == B.ZD_EINVAL
     p = B._Params(3, 16, 0, None, None, None)
     assert L.zd_build(C.byref(p), None, 0, None, C.byref(out)) == B.ZD_EINVAL  # n=0, no box
     assert L.zd_build(C.byref(p), None, 5, None, C.byref(out)) == B.ZD_EINVAL  # NULL coords
@@ -59,3 +62,25 @@ def test_argument_errors_need_no_device(L):
     assert L.zd_knn_backward(4, None, 0, 0, 1, None, None, None, None) == B.ZD_EINVAL
     assert L.zd_knn_backward(3, None, 10, 20, 1, None, None, None, None) == B.ZD_EINVAL
     assert out.value is None
+
+
+def test_params_layout_matches_the_header(tmp_path):
+    """The binding's zd_params mirror has the C struct's size and offsets."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("needs gcc")
+    import paper_2111_04182_amd._lib as B
+    fields = [f[0] for f in B._Params._fields_]
+    prog = tmp_path / "layout.c"
+    prog.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"zd.h\"\nint main(void) {\n"
+                    "  printf(\"%zu\\n\", sizeof(zd_params));\n"
+                    + "".join(f"  printf(\"%zu\\n\", offsetof(zd_params, {f}));\n" for f in fields)
+                    + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got[0] == C.sizeof(B._Params)
+    assert got[1:] == [getattr(B._Params, f).offset for f in fields]
