@@ -667,12 +667,12 @@ zd_status forest_setup(const zd_params *p, const double *xyz, int64_t n, const i
   std::vector<int4> groups;
   for (int32_t c = 0; c < C; ++c) {
     const int64_t a = offsets[c], b = offsets[c + 1], m = b - a;
-    const int nts = (int)((m + 4095) / 4096);
+    const int nts = (int)((m + kSortTileKeys - 1) / kSortTileKeys);
     const int first = (int)tiles.size();
     for (int lt = 0; lt < nts; ++lt) {
-      const int64_t st = a + (int64_t)lt * 4096;
-      tiles.push_back(make_int4((int)st, (int)std::min<int64_t>(4096, b - st), 256 * first + lt,
-                                nts));
+      const int64_t st = a + (int64_t)lt * kSortTileKeys;
+      tiles.push_back(make_int4((int)st, (int)std::min<int64_t>(kSortTileKeys, b - st),
+                                256 * first + lt, nts));
     }
     for (int64_t g = a; g < b; g += 64)
       groups.push_back(make_int4((int)g, (int)std::min<int64_t>(g + 63, b - 1), (int)a, (int)(b - 1)));

@@ -217,8 +217,10 @@ hipError_t exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_
 
 // Stable LSD radix sort of (key, value) pairs by key bits [0, key_bits).
 // Sorted pairs end in (key, val); key_tmp/val_tmp are scratch of n entries.
-// With `tiles` (device, ntiles entries of {start, count, count base, tiles
-// in segment}) each segment of the array is sorted on its own.
+// With `tiles` (device, ntiles entries of {start, count <= kSortTileKeys,
+// count base, tiles in segment}) each segment of the array is sorted on its
+// own.
+constexpr int kSortTileKeys = 4096;  // keys per sort workgroup (256 digits each)
 hipError_t radix_sort_pairs(uint64_t *key, int32_t *val, uint64_t *key_tmp, int32_t *val_tmp,
                             int64_t n, int key_bits, hipStream_t s, const int4 *tiles = nullptr,
                             int ntiles = 0);

@@ -487,8 +487,21 @@ __device__ __forceinline__ void bind_lds(WaveSearch<D, K, E> &s, char *smem, int
   }
 }
 
+// Register budget of the all-points kernel.  At k = 10 it needs 85 VGPRs
+// (5 wavefronts per SIMD); capped at 80 it keeps 6 resident and spills 7
+// dwords to scratch (reloaded once per node or leaf step, never inside the
+// insertion), which measured 3-4% faster.  At k = 12, 98 VGPRs (4 per SIMD)
+// capped at 96 gives 5 and measured 7% faster.  Other buckets keep the
+// compiler's choice (k = 12 capped at 80 spills inside the insertion and
+// runs twice as long).
+template <int K>
+constexpr int knn_all_min_waves() {
+  return K == 10 ? 6 : (K == 12 ? 5 : 1);
+}
+
 template <int D, int K>
-__global__ void __launch_bounds__(256) k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(knn_all_min_waves<K>())))
+k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
                                                  double *__restrict__ out_d2,
                                                  const int4 *__restrict__ groups, int64_t ngroups) {
   extern __shared__ __align__(16) char smem[];

@@ -7,7 +7,8 @@
 // stable scatter.  Inside a tile, each 64-lane wavefront ranks 64 keys at a
 // time: eight ballots find the lanes holding the same digit, and a per-wave
 // digit counter in LDS carries the running rank across rounds, so equal keys
-// keep their input order (ties stay in ascending id order).
+// keep their input order (ties stay in ascending id order).  The tile is
+// reordered by digit in LDS before it is written, so the stores coalesce.
 #include "zd_internal.h"
 
 namespace zd {
@@ -18,6 +19,8 @@ constexpr int kSortThreads = 256;  // 4 wavefronts
 constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys
+static_assert(kSortTile == kSortTileKeys, "tile tables assume kSortTileKeys keys per tile");
+static_assert(kSortThreads == kRadix, "one thread per digit");
 constexpr int kWaveSpan = 64 * kSortItems;            // keys per wave per tile
 
 __device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) {
@@ -66,12 +69,38 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_count(const uint64_t *ke
   counts[ti.cbase + (int64_t)threadIdx.x * ti.nts] = hist[threadIdx.x];
 }
 
+// Exclusive prefix sum of one int per thread over the workgroup; `wsum`
+// holds one int per wavefront.
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t x, int32_t *wsum) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  int32_t inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int32_t add = 0;
+#pragma unroll
+  for (int i = 0; i < kSortWaves; ++i) add += i < w ? wsum[i] : 0;
+  return inc - x + add;
+}
+
+// Stable scatter of one tile.  The tile's pairs are first ordered by digit
+// in LDS (local position = tile-local start of the digit + the pair's rank
+// among the tile's pairs of that digit), then written out in that order, so
+// consecutive lanes store to consecutive addresses of one digit's run.
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const uint64_t *__restrict__ key_in, const int32_t *__restrict__ val_in,
     uint64_t *__restrict__ key_out, int32_t *__restrict__ val_out, int64_t n, int shift,
     const int32_t *__restrict__ offsets, int ntiles, const int4 *tiles) {
   __shared__ int32_t wcount[kSortWaves][kRadix];
-  __shared__ int32_t gbase[kRadix];
+  __shared__ int32_t gbase[kRadix];  // output position of local slot 0 of each digit
+  __shared__ int32_t wsum[kSortWaves];
+  __shared__ uint64_t skey[kSortTile];
+  __shared__ int32_t sval[kSortTile];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
 #pragma unroll
@@ -106,6 +135,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
   }
   __syncthreads();
   {
+    // thread d: the digit's per-wave starts, then its start in the tile
     const int d = threadIdx.x;
     int32_t run = 0;
 #pragma unroll
@@ -114,18 +144,28 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
       wcount[i][d] = run;
       run += t;
     }
-    gbase[d] = offsets[ti.cbase + (int64_t)d * ti.nts];
+    const int32_t start = block_exclusive_scan(run, wsum);
+#pragma unroll
+    for (int i = 0; i < kSortWaves; ++i) wcount[i][d] += start;
+    gbase[d] = offsets[ti.cbase + (int64_t)d * ti.nts] - start;
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     int64_t i = base + r * 64 + lane;
     if (i < ti.end) {
-      uint32_t d = digit_of(k[r], shift);
-      int64_t pos = (int64_t)gbase[d] + wcount[w][d] + rank[r];
-      key_out[pos] = k[r];
-      val_out[pos] = v[r];
+      const int32_t lp = wcount[w][digit_of(k[r], shift)] + rank[r];
+      skey[lp] = k[r];
+      sval[lp] = v[r];
     }
+  }
+  __syncthreads();
+  const int32_t cnt = (int32_t)(ti.end - ti.start);
+  for (int32_t i = threadIdx.x; i < cnt; i += kSortThreads) {
+    const uint64_t kk = skey[i];
+    const int64_t pos = (int64_t)gbase[digit_of(kk, shift)] + i;
+    key_out[pos] = kk;
+    val_out[pos] = sval[i];
   }
 }
 
