@@ -79,7 +79,7 @@ typedef enum {
  *   query_waves: launch shape of this tree's k-NN queries: wavefronts per
  *               workgroup, 1, 2 or 4 (0 means 1).  Each wavefront answers 64
  *               queries whatever the value; it changes only how wavefronts are
- *               packed into workgroups, never the rows.  For k > 20 (per-lane
+ *               packed into workgroups, never the rows.  For k > 32 (per-lane
  *               candidate sets in LDS) the value is lowered, if needed, until
  *               the workgroup's LDS fits in one CU.  Not in the paper: a tuning
  *               knob of this implementation. */

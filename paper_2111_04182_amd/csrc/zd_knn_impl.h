@@ -65,7 +65,9 @@ struct Heap {
   template <bool kSplit = false>
   __device__ __forceinline__ void offer(double dd, int32_t q) {
     if (!(dd <= d[K - 1])) return;
-    if constexpr (kSplit && K >= 8) {
+    if constexpr (K >= kSegFrom) {
+      this->template shift_seg<K>(dd, q);
+    } else if constexpr (kSplit && K >= 8) {
       offer_split(dd, q);
     } else {
       bool lt[K];
@@ -75,6 +77,50 @@ struct Heap {
       for (int j = K - 1; j > 0; --j) {
         // slot j takes its left neighbour if the candidate precedes that
         // neighbour, else the candidate if it precedes slot j, else stays
+        const double nd = lt[j - 1] ? d[j - 1] : (lt[j] ? dd : d[j]);
+        const int32_t ni = lt[j - 1] ? id[j - 1] : (lt[j] ? q : id[j]);
+        d[j] = nd;
+        id[j] = ni;
+      }
+      if (lt[0]) {
+        d[0] = dd;
+        id[0] = q;
+      }
+    }
+  }
+
+  // For k in (20, 32]: the shift in segments of kSeg slots, top segment
+  // first.  Segment [A, B) always shifts (its lowest slot takes slot A-1's
+  // old entry if the candidate precedes that entry), and the segment below
+  // runs only when some lane's candidate does.  Most entries land near the
+  // k-th slot, so most insertions touch one segment.
+  static constexpr int kSegFrom = 24;
+  static constexpr int kSeg = 8;
+  template <int B>
+  __device__ __forceinline__ void shift_seg(double dd, int32_t q) {
+    constexpr int A = B > kSeg ? B - kSeg : 0;
+    bool lt[B - A];
+#pragma unroll
+    for (int j = A; j < B; ++j) lt[j - A] = cand_lt(dd, q, d[j], id[j]);
+    if constexpr (A > 0) {
+      const bool low = cand_lt(dd, q, d[A - 1], id[A - 1]);
+      const double cd = d[A - 1];
+      const int32_t ci = id[A - 1];
+#pragma unroll
+      for (int j = B - 1; j > A; --j) {
+        const double nd = lt[j - 1 - A] ? d[j - 1] : (lt[j - A] ? dd : d[j]);
+        const int32_t ni = lt[j - 1 - A] ? id[j - 1] : (lt[j - A] ? q : id[j]);
+        d[j] = nd;
+        id[j] = ni;
+      }
+      const double nd = low ? cd : (lt[0] ? dd : d[A]);
+      const int32_t ni = low ? ci : (lt[0] ? q : id[A]);
+      d[A] = nd;
+      id[A] = ni;
+      if (__ballot(low) != 0) this->template shift_seg<A>(dd, q);
+    } else {
+#pragma unroll
+      for (int j = B - 1; j > 0; --j) {
         const double nd = lt[j - 1] ? d[j - 1] : (lt[j] ? dd : d[j]);
         const int32_t ni = lt[j - 1] ? id[j - 1] : (lt[j] ? q : id[j]);
         d[j] = nd;
@@ -141,7 +187,7 @@ struct Heap {
   }
 };
 
-// For k > 20 the candidate set is a binary max-heap of the k best (d2, id)
+// For k > 32 the candidate set is a binary max-heap of the k best (d2, id)
 // per lane, kept in LDS (slot-major: slot s of lane l at [s * 64 + l], so a
 // lane's bank never depends on the slot it touches).  Replacing the root and
 // sifting down costs O(log k) instead of the O(k) register shift, and the
@@ -235,8 +281,6 @@ struct HeapFor {
     using type = LdsHeap<KK>;            \
     static constexpr bool lds = true;    \
   };
-ZD_LDS_HEAP(24)
-ZD_LDS_HEAP(32)
 ZD_LDS_HEAP(40)
 ZD_LDS_HEAP(50)
 ZD_LDS_HEAP(64)
@@ -469,7 +513,7 @@ constexpr size_t wave_lds_bytes() {
 }
 // Wavefronts per workgroup of a query launch: the requested 1, 2 or 4,
 // halved while the workgroup's LDS would exceed one CU's 160 KiB (only the
-// k > 20 buckets, whose candidate sets live in LDS, come near it).
+// k > 32 buckets, whose candidate sets live in LDS, come near it).
 template <int K>
 int fit_waves(int want) {
   int w = want == 2 || want == 4 ? want : 1;
