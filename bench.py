@@ -46,6 +46,14 @@ sys.path.insert(0, ROOT)
 # code is built without fused operations, so each lane retires one op/clock).
 FP64_VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per point of one build (3D, 8 sort passes): Morton
+# keys (24 B read, 8 B key + 4 B id written), 8 radix passes (8 B counted +
+# 12 B read + 12 B written each), the gather into sorted order (4 B id +
+# 24 B read, 24 B + 4 B id map written), and the tree pass (8 B keys read,
+# 1 B split bit written and read, 4 + 4 B flag scan, 24 B coordinates read
+# for the leaf boxes, 4 B leaf map, about 12 B of node records).
+BUILD_BYTES_PER_POINT = (24 + 12) + 8 * (8 + 12 + 12) + (4 + 24 + 24 + 4) + (8 + 2 + 8 + 24 + 4 + 12)
 # Algorithmic FP64 work per all-points query on this workload (3D uniform,
 # 10M points, k = 10), by leaf size: mean candidate distances (8 ops each:
 # 3 sub, 3 mul, 2 add) and box tests (17 ops each) of the serial oracle's
@@ -236,6 +244,7 @@ def main():
                                "k-NN, insert 1M, delete 1M, all-points k-NN",
                    "n": n, "k": k, "leaf_size": L, "insert": m, "delete": m},
         "build_mpts_s": n / (ph["build"] / 1e3) / 1e6,
+        "build_hbm_frac": n * BUILD_BYTES_PER_POINT / (ph["build"] / 1e3) / (HBM_PEAK_GBS * 1e9),
         "query_qps": n / q_launch_s,
         "insert_mpts_s": m / (ph["insert"] / 1e3) / 1e6,
         "delete_mpts_s": m / (ph["delete"] / 1e3) / 1e6,

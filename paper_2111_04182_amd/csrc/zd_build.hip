@@ -341,11 +341,15 @@ __global__ void __launch_bounds__(kLeafBlock)
   const int32_t begin = j == 0 ? 0 : inode[j - 1].split + 1;
   const int32_t end = j == I ? (int32_t)n : inode[j].split + 1;
   leaf_begin[j] = begin;
-  if (j == I) leaf_begin[I + 1] = (int32_t)n;
+  // leaf_of[s] for s < n-1 already holds the exclusive count of splits
+  // before s, which is the leaf of s; only the last point is left
+  if (j == I) {
+    leaf_begin[I + 1] = (int32_t)n;
+    leaf_of[n - 1] = I;
+  }
   double lo[3] = {INFINITY, INFINITY, D == 3 ? INFINITY : 0.0};
   double hi[3] = {-INFINITY, -INFINITY, D == 3 ? -INFINITY : 0.0};
   for (int32_t s = begin; s < end; ++s) {
-    leaf_of[s] = (int32_t)j;
     double x = X[s], y = Y[s];
     lo[0] = fmin(lo[0], x); hi[0] = fmax(hi[0], x);
     lo[1] = fmin(lo[1], y); hi[1] = fmax(hi[1], y);
@@ -447,7 +451,9 @@ hipError_t build_tree_links(int dim, int leaf_size, int64_t n, const BuildBuffer
       k_split_flags<<<grid_n, 256, 0, s>>>(sb, b.seg, n, leaf_size, b.seg_leaf, b.flag);
       e = hipGetLastError();
     }
-    // exclusive positions overwrite leaf_of (free until the leaf pass)
+    // exclusive split counts: the node number of each split for the
+    // compaction, and at the same time leaf_of (the splits before a point
+    // number its leaf; the leaf pass adds the last point)
     if (e == hipSuccess)
       e = exclusive_scan_i32(b.flag, b.leaf_of, n - 1, b.meta + kMetaInternal, s);
     if (e == hipSuccess) {
