@@ -346,7 +346,10 @@ struct WaveSearch {
   // which enters as (+inf, INT_MAX) and so never precedes the k-th entry.
   // (All-points groups only: an external query group covers many more tree
   // points than its 64 queries and measured slower with a shared window;
-  // its lanes score their own leaves instead.)
+  // its lanes score their own leaves instead.  This shared order, one
+  // position at a time in LDS chunks of 64, serves the LDS-heap buckets,
+  // whose stage holds 64 entries; the register buckets use
+  // prescore_near_first.)
   __device__ __forceinline__ void prescore(int64_t a, int64_t b, int64_t own) {
     const int lane = threadIdx.x & 63;
     for (int64_t c = a; c <= b; c += 64) {
@@ -370,6 +373,39 @@ struct WaveSearch {
       }
       __builtin_amdgcn_wave_barrier();
     }
+    skip_lo = uni((int32_t)a);
+    skip_hi = uni((int32_t)b);
+  }
+
+  // The same positions, each lane in its own order: lane l (own position
+  // a + o) takes at step s the position a + ((o + m) mod cnt) for s odd and
+  // a + ((o - m) mod cnt) for s even, m = (s + 1) / 2, so it meets its
+  // Morton neighbours first and every other position of [a, b] exactly
+  // once.  Its k-th distance tightens sooner than in the shared order, and
+  // fewer later candidates enter.  The stage holds the whole window.
+  __device__ __forceinline__ void prescore_near_first(int64_t a, int64_t b, int64_t own) {
+    const int lane = threadIdx.x & 63;
+    const int cnt = (int)(b - a + 1);  // <= 64 + 2 kPrescore entries of the stage
+    for (int j = lane; j < cnt; j += 64) {
+      Cand q;
+      q.x = t.X[a + j];
+      q.y = t.Y[a + j];
+      q.z = D == 3 ? t.Z[a + j] : 0.0;
+      q.id = t.id[a + j];
+      q.pad = 0;
+      stage[j] = q;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int o = valid ? (int)(own - a) : 0;
+    for (int s = 1; s < cnt; ++s) {
+      const int m = (s + 1) >> 1;
+      int j = (s & 1) ? o + m : o - m;
+      j = j >= cnt ? j - cnt : (j < 0 ? j + cnt : j);
+      const Cand q = stage[j];
+      const double dd = dist2<D>(px, py, pz, q.x, q.y, q.z);
+      h.offer(dd, q.id);
+    }
+    __builtin_amdgcn_wave_barrier();
     skip_lo = uni((int32_t)a);
     skip_hi = uni((int32_t)b);
   }
@@ -506,11 +542,14 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t h, uint32_t nb) {
 }
 
 // All-points rows: wavefront w answers sorted positions [64w, 64w + 64).
-// LDS per wavefront: the 64-entry candidate stage, plus the heap for large k
+// LDS per wavefront: the candidate stage (the whole prescore window for the
+// register candidate sets, 64 entries for the LDS heaps), plus the heap
 template <int K>
 constexpr size_t wave_lds_bytes() {
-  return 64 * sizeof(Cand) + (HeapFor<K>::lds ? (size_t)K * 64 * (sizeof(double) + sizeof(int32_t)) : 0);
+  return (HeapFor<K>::lds ? 64 : 64 + 2 * kPrescore) * sizeof(Cand) +
+         (HeapFor<K>::lds ? (size_t)K * 64 * (sizeof(double) + sizeof(int32_t)) : 0);
 }
+
 // Wavefronts per workgroup of a query launch: the requested 1, 2 or 4,
 // halved while the workgroup's LDS would exceed one CU's 160 KiB (only the
 // k > 32 buckets, whose candidate sets live in LDS, come near it).
@@ -583,7 +622,10 @@ k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
   // the group's own points and kPrescore on either side (Morton neighbours
   // of every lane).  This tightens every lane's k-th distance before the
   // walk, which then skips these positions.
-  s.prescore(max(c_lo, g0 - kPrescore), min(c_hi, last + kPrescore), g0 + lane);
+  if constexpr (HeapFor<K>::lds)
+    s.prescore(max(c_lo, g0 - kPrescore), min(c_hi, last + kPrescore), g0 + lane);
+  else
+    s.prescore_near_first(max(c_lo, g0 - kPrescore), min(c_hi, last + kPrescore), g0 + lane);
   // lowest common ancestor of the group's leaves
   const int32_t lf = uni(t.leaf_of[g0]), ll = uni(t.leaf_of[last]);
   int32_t G = ~lf;
