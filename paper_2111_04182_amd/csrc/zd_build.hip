@@ -290,7 +290,8 @@ __device__ __forceinline__ int32_t fetch_i32(int32_t *p) { return atomicOr(p, 0)
 
 constexpr int kLeafBlock = 256;
 
-// One thread per leaf: the leaf's point range and tight box, then the climb.
+// One thread per leaf: the leaf's point range and tight box (from points the
+// workgroup stages in LDS), then the climb.
 // A node spanning leaves [l, r] hangs below the neighbouring split (l-1 or r)
 // with the lower bit; each node is finished by the second child to arrive.
 // Workgroup w takes leaves [256w, 256w + 256).  An internal node whose whole
@@ -310,6 +311,8 @@ __global__ void __launch_bounds__(kLeafBlock)
   __shared__ int32_t s_cnt[kLeafBlock];      // arrivals at local node j0+t
   __shared__ int32_t s_end[kLeafBlock][2];   // outer leaf bound of each child
   __shared__ double s_box[kLeafBlock][2][6]; // box of each child (lo, hi)
+  __shared__ double s_pt[3][kLeafBlock];     // a chunk of the window's points
+  __shared__ int32_t s_range[2];             // the window's points [P0, P1)
   const int t = threadIdx.x;
   const int64_t j0 = (int64_t)blockIdx.x * kLeafBlock;
   const int32_t I = meta[kMetaInternal];
@@ -337,27 +340,49 @@ __global__ void __launch_bounds__(kLeafBlock)
   }
   __syncthreads();
   const int64_t j = j0 + t;
-  if (j > I) return;
-  const int32_t begin = j == 0 ? 0 : inode[j - 1].split + 1;
-  const int32_t end = j == I ? (int32_t)n : inode[j].split + 1;
-  leaf_begin[j] = begin;
-  // leaf_of[s] for s < n-1 already holds the exclusive count of splits
-  // before s, which is the leaf of s; only the last point is left
-  if (j == I) {
-    leaf_begin[I + 1] = (int32_t)n;
-    leaf_of[n - 1] = I;
-  }
-  double lo[3] = {INFINITY, INFINITY, D == 3 ? INFINITY : 0.0};
-  double hi[3] = {-INFINITY, -INFINITY, D == 3 ? -INFINITY : 0.0};
-  for (int32_t s = begin; s < end; ++s) {
-    double x = X[s], y = Y[s];
-    lo[0] = fmin(lo[0], x); hi[0] = fmax(hi[0], x);
-    lo[1] = fmin(lo[1], y); hi[1] = fmax(hi[1], y);
-    if (D == 3) {
-      double z = Z[s];
-      lo[2] = fmin(lo[2], z); hi[2] = fmax(hi[2], z);
+  const bool own = j <= I;  // this thread's leaf exists
+  int32_t begin = 0, end = 0;
+  if (own) {
+    begin = j == 0 ? 0 : inode[j - 1].split + 1;
+    end = j == I ? (int32_t)n : inode[j].split + 1;
+    leaf_begin[j] = begin;
+    // leaf_of[s] for s < n-1 already holds the exclusive count of splits
+    // before s, which is the leaf of s; only the last point is left
+    if (j == I) {
+      leaf_begin[I + 1] = (int32_t)n;
+      leaf_of[n - 1] = I;
     }
   }
+  // Leaf boxes.  The window's leaves hold the contiguous points [P0, P1);
+  // the workgroup reads them in coalesced chunks into LDS and each thread
+  // folds in the part of the chunk that belongs to its leaf.
+  if (t == 0) s_range[0] = begin;
+  if (j == min(j0 + kLeafBlock - 1, (int64_t)I)) s_range[1] = end;
+  __syncthreads();
+  const int32_t P0 = s_range[0], P1 = s_range[1];
+  double lo[3] = {INFINITY, INFINITY, D == 3 ? INFINITY : 0.0};
+  double hi[3] = {-INFINITY, -INFINITY, D == 3 ? -INFINITY : 0.0};
+  for (int32_t c0 = P0; c0 < P1; c0 += kLeafBlock) {
+    const int32_t p = c0 + t;
+    if (p < P1) {
+      s_pt[0][t] = X[p];
+      s_pt[1][t] = Y[p];
+      if (D == 3) s_pt[2][t] = Z[p];
+    }
+    __syncthreads();
+    const int32_t a = max(begin, c0), b = min(end, c0 + kLeafBlock);
+    for (int32_t s = a; s < b; ++s) {
+      const double x = s_pt[0][s - c0], y = s_pt[1][s - c0];
+      lo[0] = fmin(lo[0], x); hi[0] = fmax(hi[0], x);
+      lo[1] = fmin(lo[1], y); hi[1] = fmax(hi[1], y);
+      if (D == 3) {
+        const double z = s_pt[2][s - c0];
+        lo[2] = fmin(lo[2], z); hi[2] = fmax(hi[2], z);
+      }
+    }
+    __syncthreads();
+  }
+  if (!own) return;
   auto bit_of = [&](int32_t x) -> int32_t {
     const int64_t q = (int64_t)x - (j0 - 1);
     return (q >= 0 && q <= kLeafBlock) ? s_bit[q] : inode[x].bit;
