@@ -235,28 +235,44 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const int32_t *in,
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
+// The tile passes through LDS twice so that global loads and stores are
+// coalesced while each thread scans kScanItems consecutive entries (one
+// padding slot per 32 entries keeps the strided LDS accesses conflict-free).
+__device__ __forceinline__ int scan_slot(int idx) { return idx + (idx >> 5); }
+
 __global__ void __launch_bounds__(kScanThreads) k_scan_down(const int32_t *in, int32_t *out,
                                                             int64_t n, const int32_t *offsets,
                                                             int32_t *total_out) {
-  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  __shared__ int32_t tile[kScanTile + kScanTile / 32];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    const int idx = j * kScanThreads + threadIdx.x;
+    tile[scan_slot(idx)] = base + idx < n ? in[base + idx] : 0;
+  }
+  __syncthreads();
   int32_t v[kScanItems];
   int32_t acc = 0;
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
-    int64_t i = base + j;
-    v[j] = i < n ? in[i] : 0;
+    v[j] = tile[scan_slot(threadIdx.x * kScanItems + j)];
     acc += v[j];
   }
   int32_t total;
   int32_t run = block_exclusive_scan(acc, &total) + (offsets ? offsets[blockIdx.x] : 0);
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
-    int64_t i = base + j;
-    if (i < n) out[i] = run;
+    tile[scan_slot(threadIdx.x * kScanItems + j)] = run;
     run += v[j];
   }
   if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1)
     *total_out = run;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    const int idx = j * kScanThreads + threadIdx.x;
+    if (base + idx < n) out[base + idx] = tile[scan_slot(idx)];
+  }
 }
 
 hipError_t exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total,

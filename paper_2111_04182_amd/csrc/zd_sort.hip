@@ -15,12 +15,12 @@ namespace zd {
 
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
-constexpr int kSortThreads = 256;  // 4 wavefronts
+constexpr int kSortThreads = 512;  // 8 wavefronts
 constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kSortItems = 16;
+constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys
 static_assert(kSortTile == kSortTileKeys, "tile tables assume kSortTileKeys keys per tile");
-static_assert(kSortThreads == kRadix, "one thread per digit");
+static_assert(kSortThreads >= kRadix, "a thread per digit");
 constexpr int kWaveSpan = 64 * kSortItems;            // keys per wave per tile
 
 __device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) {
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_count(const uint64_t *ke
                                                               int shift, int32_t *counts,
                                                               int ntiles, const int4 *tiles) {
   __shared__ int32_t hist[kRadix];
-  hist[threadIdx.x] = 0;
+  if (threadIdx.x < kRadix) hist[threadIdx.x] = 0;
   __syncthreads();
   const TileInfo ti = tile_info(tiles, n, ntiles);
 #pragma unroll 4
@@ -66,12 +66,12 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_count(const uint64_t *ke
     if (i < ti.end) atomicAdd(&hist[digit_of(key[i], shift)], 1);
   }
   __syncthreads();
-  counts[ti.cbase + (int64_t)threadIdx.x * ti.nts] = hist[threadIdx.x];
+  if (threadIdx.x < kRadix) counts[ti.cbase + (int64_t)threadIdx.x * ti.nts] = hist[threadIdx.x];
 }
 
 // Exclusive prefix sum of one int per thread over the workgroup; `wsum`
-// holds one int per wavefront.
-__device__ __forceinline__ int32_t block_exclusive_scan(int32_t x, int32_t *wsum) {
+// holds one int per wavefront.  (Threads past the 256 digits pass 0.)
+__device__ __forceinline__ int32_t digit_exclusive_scan(int32_t x, int32_t *wsum) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   int32_t inc = x;
@@ -103,8 +103,9 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
   __shared__ int32_t sval[kSortTile];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
+  if (threadIdx.x < kRadix)
 #pragma unroll
-  for (int i = 0; i < kSortWaves; ++i) wcount[i][threadIdx.x] = 0;
+    for (int i = 0; i < kSortWaves; ++i) wcount[i][threadIdx.x] = 0;
   __syncthreads();
 
   const TileInfo ti = tile_info(tiles, n, ntiles);
@@ -138,16 +139,20 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     // thread d: the digit's per-wave starts, then its start in the tile
     const int d = threadIdx.x;
     int32_t run = 0;
+    if (d < kRadix) {
 #pragma unroll
-    for (int i = 0; i < kSortWaves; ++i) {
-      int32_t t = wcount[i][d];
-      wcount[i][d] = run;
-      run += t;
+      for (int i = 0; i < kSortWaves; ++i) {
+        int32_t t = wcount[i][d];
+        wcount[i][d] = run;
+        run += t;
+      }
     }
-    const int32_t start = block_exclusive_scan(run, wsum);
+    const int32_t start = digit_exclusive_scan(run, wsum);
+    if (d < kRadix) {
 #pragma unroll
-    for (int i = 0; i < kSortWaves; ++i) wcount[i][d] += start;
-    gbase[d] = offsets[ti.cbase + (int64_t)d * ti.nts] - start;
+      for (int i = 0; i < kSortWaves; ++i) wcount[i][d] += start;
+      gbase[d] = offsets[ti.cbase + (int64_t)d * ti.nts] - start;
+    }
   }
   __syncthreads();
 #pragma unroll
