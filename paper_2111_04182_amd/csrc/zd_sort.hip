@@ -15,9 +15,9 @@ namespace zd {
 
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
-constexpr int kSortThreads = 512;  // 8 wavefronts
+constexpr int kSortThreads = 1024;  // 16 wavefronts
 constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kSortItems = 8;
+constexpr int kSortItems = 4;
 constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys
 static_assert(kSortTile == kSortTileKeys, "tile tables assume kSortTileKeys keys per tile");
 static_assert(kSortThreads >= kRadix, "a thread per digit");
