@@ -58,6 +58,25 @@ struct Heap {
 
   __device__ __forceinline__ double kth() const { return d[K - 1]; }
 
+  // lt[j - A] = (dd, q) precedes slot j, for j in [A, B).  The distance
+  // compare decides unless the distances are equal; the id compares run
+  // only when some lane meets an equal distance in the range.  (Used by the
+  // segmented shift; for k <= 20 the three compares per slot measured
+  // faster than the extra branch.)
+  template <int A, int B>
+  __device__ __forceinline__ void precedes(double dd, int32_t q, bool *lt) const {
+    bool tie = false;
+#pragma unroll
+    for (int j = A; j < B; ++j) {
+      lt[j - A] = dd < d[j];
+      tie = tie | (dd == d[j]);
+    }
+    if (__ballot(tie) != 0) {
+#pragma unroll
+      for (int j = A; j < B; ++j) lt[j - A] = lt[j - A] | ((dd == d[j]) & (q < id[j]));
+    }
+  }
+
   // insert(N, q, k) of Algorithms 2-3: enters iff it precedes the k-th entry.
   // The first test is one compare; a tie with the k-th distance falls through
   // to the exact (d2, id) comparisons, which then change nothing if the
@@ -100,8 +119,7 @@ struct Heap {
   __device__ __forceinline__ void shift_seg(double dd, int32_t q) {
     constexpr int A = B > kSeg ? B - kSeg : 0;
     bool lt[B - A];
-#pragma unroll
-    for (int j = A; j < B; ++j) lt[j - A] = cand_lt(dd, q, d[j], id[j]);
+    precedes<A, B>(dd, q, lt);
     if constexpr (A > 0) {
       const bool low = cand_lt(dd, q, d[A - 1], id[A - 1]);
       const double cd = d[A - 1];
