@@ -80,7 +80,7 @@ typedef enum {
  *               workgroup, 1, 2 or 4 (0 means 1).  Each wavefront answers 64
  *               queries whatever the value; it changes only how wavefronts are
  *               packed into workgroups, never the rows.  For k > 32 (per-lane
- *               candidate sets in LDS) the value is lowered, if needed, until
+ *               candidate sets partly in LDS) the value is lowered, if needed, until
  *               the workgroup's LDS fits in one CU.  Not in the paper: a tuning
  *               knob of this implementation. */
 typedef struct {

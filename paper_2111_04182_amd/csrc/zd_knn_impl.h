@@ -61,7 +61,7 @@ struct Heap {
   // lt[j - A] = (dd, q) precedes slot j, for j in [A, B).  The distance
   // compare decides unless the distances are equal; the id compares run
   // only when some lane meets an equal distance in the range.  (Used by the
-  // segmented shift; for k <= 20 the three compares per slot measured
+  // segmented shift; for k <= 16 the three compares per slot measured
   // faster than the extra branch.)
   template <int A, int B>
   __device__ __forceinline__ void precedes(double dd, int32_t q, bool *lt) const {
@@ -108,12 +108,12 @@ struct Heap {
     }
   }
 
-  // For k in (20, 32]: the shift in segments of kSeg slots, top segment
+  // For k in (16, 32]: the shift in segments of kSeg slots, top segment
   // first.  Segment [A, B) always shifts (its lowest slot takes slot A-1's
   // old entry if the candidate precedes that entry), and the segment below
   // runs only when some lane's candidate does.  Most entries land near the
   // k-th slot, so most insertions touch one segment.
-  static constexpr int kSegFrom = 24;
+  static constexpr int kSegFrom = 20;
   static constexpr int kSeg = 8;
   template <int B>
   __device__ __forceinline__ void shift_seg(double dd, int32_t q) {
@@ -205,7 +205,7 @@ struct Heap {
   }
 };
 
-// For k > 32 the candidate set is a binary max-heap of the k best (d2, id)
+// For k > 50 the candidate set is a binary max-heap of the k best (d2, id)
 // per lane, kept in LDS (slot-major: slot s of lane l at [s * 64 + l], so a
 // lane's bank never depends on the slot it touches).  Replacing the root and
 // sifting down costs O(log k) instead of the O(k) register shift, and the
@@ -288,21 +288,160 @@ struct LdsHeap {
   }
 };
 
+// For k in (32, 50] the k best are split: the lower M = K - R slots,
+// sorted, in LDS (slot-major like the heap above), the upper R slots in
+// registers with the segmented shift.  Entries mostly land near the k-th
+// slot, so most insertions stay in registers; one that reaches below them
+// shifts the LDS part of its own lane up by one.  The largest LDS entry is
+// mirrored in registers for the boundary test.  This keeps 2 wavefronts
+// per SIMD where the whole set in LDS (the heap) allowed one.  (k = 51-64
+// keeps the heap: with R = 24, 40 or 48 the split set measured slower, the
+// larger R overflowing the register file.)
+template <int K, int R_>
+struct SplitSet {
+  static constexpr int R = R_;
+  static constexpr int M = K - R;
+  static constexpr int kSeg = 8;
+  double d[R];    // slots M .. K-1
+  int32_t id[R];
+  double md;      // slot M-1
+  int32_t mi;
+  double *ld;     // [M][64] this wavefront's lower slots
+  int32_t *li;
+
+  __device__ __forceinline__ void bind(double *d_, int32_t *i_) {
+    ld = d_;
+    li = i_;
+  }
+
+  // every register slot and slot M-1 lie above the K-k padding slots
+  // (K - k < M in every bucket that uses this set), so only the LDS part
+  // holds padding
+  __device__ __forceinline__ void init(int k, bool live) {
+    const int lane = threadIdx.x & 63;
+    for (int j = 0; j < M; ++j) {
+      const bool used = live && j >= K - k;
+      ld[j * 64 + lane] = used ? INFINITY : -INFINITY;
+      li[j * 64 + lane] = used ? INT_MAX : INT_MIN;
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      d[j] = live ? INFINITY : -INFINITY;
+      id[j] = live ? INT_MAX : INT_MIN;
+    }
+    md = live ? INFINITY : -INFINITY;
+    mi = live ? INT_MAX : INT_MIN;
+  }
+
+  __device__ __forceinline__ double kth() const { return d[R - 1]; }
+
+  template <int A, int B>
+  __device__ __forceinline__ void precedes(double dd, int32_t q, bool *lt) const {
+    bool tie = false;
+#pragma unroll
+    for (int j = A; j < B; ++j) {
+      lt[j - A] = dd < d[j];
+      tie = tie | (dd == d[j]);
+    }
+    if (__ballot(tie) != 0) {
+#pragma unroll
+      for (int j = A; j < B; ++j) lt[j - A] = lt[j - A] | ((dd == d[j]) & (q < id[j]));
+    }
+  }
+
+  // register slots [A, B), top segment first; below slot 0 is slot M-1
+  template <int B>
+  __device__ __forceinline__ void shift(double dd, int32_t q) {
+    constexpr int A = B > kSeg ? B - kSeg : 0;
+    bool lt[B - A];
+    precedes<A, B>(dd, q, lt);
+    const double cd = A > 0 ? d[A > 0 ? A - 1 : 0] : md;
+    const int32_t ci = A > 0 ? id[A > 0 ? A - 1 : 0] : mi;
+    const bool low = cand_lt(dd, q, cd, ci);
+#pragma unroll
+    for (int j = B - 1; j > A; --j) {
+      const double nd = lt[j - 1 - A] ? d[j - 1] : (lt[j - A] ? dd : d[j]);
+      const int32_t ni = lt[j - 1 - A] ? id[j - 1] : (lt[j - A] ? q : id[j]);
+      d[j] = nd;
+      id[j] = ni;
+    }
+    const double nd = low ? cd : (lt[0] ? dd : d[A]);
+    const int32_t ni = low ? ci : (lt[0] ? q : id[A]);
+    d[A] = nd;
+    id[A] = ni;
+    if (__ballot(low) != 0) {
+      if constexpr (A > 0)
+        this->template shift<A>(dd, q);
+      else if (low)
+        lds_insert(dd, q);
+    }
+  }
+
+  // the candidate precedes slot M-1, whose entry has moved to register
+  // slot 0: shift the larger LDS entries up and place it
+  __device__ __forceinline__ void lds_insert(double dd, int32_t q) {
+    const int lane = threadIdx.x & 63;
+    int j = M - 1;
+    for (; j > 0; --j) {
+      const double sd = ld[(j - 1) * 64 + lane];
+      const int32_t si = li[(j - 1) * 64 + lane];
+      if (!cand_lt(dd, q, sd, si)) break;
+      ld[j * 64 + lane] = sd;
+      li[j * 64 + lane] = si;
+    }
+    ld[j * 64 + lane] = dd;
+    li[j * 64 + lane] = q;
+    md = ld[(M - 1) * 64 + lane];
+    mi = li[(M - 1) * 64 + lane];
+  }
+
+  template <bool = false>
+  __device__ __forceinline__ void offer(double dd, int32_t q) {
+    if (!(dd <= d[R - 1])) return;
+    this->template shift<R>(dd, q);
+  }
+
+  __device__ __forceinline__ void write(int k, int32_t *out_ids, double *out_d2) const {
+    const int lane = threadIdx.x & 63;
+    int o = 0;
+    for (int j = K - k; j < M; ++j, ++o) {
+      const int32_t i = li[j * 64 + lane];
+      out_ids[o] = i == INT_MAX ? -1 : i;
+      out_d2[o] = ld[j * 64 + lane];
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      out_ids[o + j] = id[j] == INT_MAX ? -1 : id[j];
+      out_d2[o + j] = d[j];
+    }
+  }
+};
+
+// Per k bucket: the candidate set, its per-lane LDS slots, and whether the
+// prescore runs in the shared order over a 64-entry stage (the LDS heap)
+// or each lane's near-first order over the whole window.
 template <int K>
 struct HeapFor {
   using type = Heap<K>;
-  static constexpr bool lds = false;
+  static constexpr int lds_slots = 0;
+  static constexpr bool shared_prescore = false;
 };
-#define ZD_LDS_HEAP(KK)                  \
-  template <>                            \
-  struct HeapFor<KK> {                   \
-    using type = LdsHeap<KK>;            \
-    static constexpr bool lds = true;    \
+#define ZD_SPLIT_SET(KK, RR)                       \
+  template <>                                      \
+  struct HeapFor<KK> {                             \
+    using type = SplitSet<KK, RR>;                 \
+    static constexpr int lds_slots = KK - RR;      \
+    static constexpr bool shared_prescore = false; \
   };
-ZD_LDS_HEAP(40)
-ZD_LDS_HEAP(50)
-ZD_LDS_HEAP(64)
-#undef ZD_LDS_HEAP
+ZD_SPLIT_SET(40, 24)
+ZD_SPLIT_SET(50, 32)
+#undef ZD_SPLIT_SET
+template <>
+struct HeapFor<64> {
+  using type = LdsHeap<64>;
+  static constexpr int lds_slots = 64;
+  static constexpr bool shared_prescore = true;
+};
 
 // withinBox(C, p, -r) of Algorithm 3, squared: p in the box and every face
 // strictly farther than the k-th d2 (never true while N holds fewer than k,
@@ -564,13 +703,14 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t h, uint32_t nb) {
 // register candidate sets, 64 entries for the LDS heaps), plus the heap
 template <int K>
 constexpr size_t wave_lds_bytes() {
-  return (HeapFor<K>::lds ? 64 : 64 + 2 * kPrescore) * sizeof(Cand) +
-         (HeapFor<K>::lds ? (size_t)K * 64 * (sizeof(double) + sizeof(int32_t)) : 0);
+  return (HeapFor<K>::shared_prescore ? 64 : 64 + 2 * kPrescore) * sizeof(Cand) +
+         (size_t)HeapFor<K>::lds_slots * 64 * (sizeof(double) + sizeof(int32_t));
 }
 
 // Wavefronts per workgroup of a query launch: the requested 1, 2 or 4,
 // halved while the workgroup's LDS would exceed one CU's 160 KiB (only the
-// k > 32 buckets, whose candidate sets live in LDS, come near it).
+// k > 32 buckets, whose candidate sets live wholly or partly in LDS, come
+// near it).
 template <int K>
 int fit_waves(int want) {
   int w = want == 2 || want == 4 ? want : 1;
@@ -582,9 +722,10 @@ template <int D, int K, bool E>
 __device__ __forceinline__ void bind_lds(WaveSearch<D, K, E> &s, char *smem, int w) {
   char *base = smem + (size_t)w * wave_lds_bytes<K>();
   s.stage = reinterpret_cast<Cand *>(base);
-  if constexpr (HeapFor<K>::lds) {
-    double *hd = reinterpret_cast<double *>(base + 64 * sizeof(Cand));
-    s.h.bind(hd, reinterpret_cast<int32_t *>(hd + (size_t)K * 64));
+  if constexpr (HeapFor<K>::lds_slots > 0) {
+    constexpr int kStage = HeapFor<K>::shared_prescore ? 64 : 64 + 2 * kPrescore;
+    double *hd = reinterpret_cast<double *>(base + kStage * sizeof(Cand));
+    s.h.bind(hd, reinterpret_cast<int32_t *>(hd + (size_t)HeapFor<K>::lds_slots * 64));
   }
 }
 
@@ -592,12 +733,14 @@ __device__ __forceinline__ void bind_lds(WaveSearch<D, K, E> &s, char *smem, int
 // (5 wavefronts per SIMD); capped at 80 it keeps 6 resident and spills 7
 // dwords to scratch (reloaded once per node or leaf step, never inside the
 // insertion), which measured 3-4% faster.  At k = 12, 98 VGPRs (4 per SIMD)
-// capped at 96 gives 5 and measured 7% faster.  Other buckets keep the
-// compiler's choice (k = 12 capped at 80 spills inside the insertion and
-// runs twice as long).
+// capped at 96 gives 5 and measured 7% faster.  At k = 24, 172 VGPRs (2 per
+// SIMD) capped at 168 gives 3 and measured 20% faster; k = 20 keeps 3 per
+// SIMD.  Other buckets keep the compiler's choice (caps that spill inside
+// the insertion, k = 12 at 80, k = 16 at 96, k = 32 at 168, run up to twice
+// as long).
 template <int K>
 constexpr int knn_all_min_waves() {
-  return K == 10 ? 6 : (K == 12 ? 5 : 1);
+  return K == 10 ? 6 : (K == 12 ? 5 : (K == 20 || K == 24 ? 3 : 1));
 }
 
 template <int D, int K>
@@ -640,7 +783,7 @@ k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
   // the group's own points and kPrescore on either side (Morton neighbours
   // of every lane).  This tightens every lane's k-th distance before the
   // walk, which then skips these positions.
-  if constexpr (HeapFor<K>::lds)
+  if constexpr (HeapFor<K>::shared_prescore)
     s.prescore(max(c_lo, g0 - kPrescore), min(c_hi, last + kPrescore), g0 + lane);
   else
     s.prescore_near_first(max(c_lo, g0 - kPrescore), min(c_hi, last + kPrescore), g0 + lane);
