@@ -108,7 +108,7 @@ struct Heap {
     }
   }
 
-  // For k in (16, 32]: the shift in segments of kSeg slots, top segment
+  // For k in (16, 24]: the shift in segments of kSeg slots, top segment
   // first.  Segment [A, B) always shifts (its lowest slot takes slot A-1's
   // old entry if the candidate precedes that entry), and the segment below
   // runs only when some lane's candidate does.  Most entries land near the
@@ -288,13 +288,14 @@ struct LdsHeap {
   }
 };
 
-// For k in (32, 50] the k best are split: the lower M = K - R slots,
+// For k in (24, 50] the k best are split: the lower M = K - R slots,
 // sorted, in LDS (slot-major like the heap above), the upper R slots in
 // registers with the segmented shift.  Entries mostly land near the k-th
 // slot, so most insertions stay in registers; one that reaches below them
 // shifts the LDS part of its own lane up by one.  The largest LDS entry is
-// mirrored in registers for the boundary test.  This keeps 2 wavefronts
-// per SIMD where the whole set in LDS (the heap) allowed one.  (k = 51-64
+// mirrored in registers for the boundary test.  This keeps 2 or 3
+// wavefronts per SIMD where the whole set in LDS (the heap) allowed one, or
+// the whole set in registers two (k = 32).  (k = 51-64
 // keeps the heap: with R = 24, 40 or 48 the split set measured slower, the
 // larger R overflowing the register file.)
 template <int K, int R_>
@@ -433,6 +434,7 @@ struct HeapFor {
     static constexpr int lds_slots = KK - RR;      \
     static constexpr bool shared_prescore = false; \
   };
+ZD_SPLIT_SET(32, 24)
 ZD_SPLIT_SET(40, 24)
 ZD_SPLIT_SET(50, 32)
 #undef ZD_SPLIT_SET
@@ -735,12 +737,13 @@ __device__ __forceinline__ void bind_lds(WaveSearch<D, K, E> &s, char *smem, int
 // insertion), which measured 3-4% faster.  At k = 12, 98 VGPRs (4 per SIMD)
 // capped at 96 gives 5 and measured 7% faster.  At k = 24, 172 VGPRs (2 per
 // SIMD) capped at 168 gives 3 and measured 20% faster; k = 20 keeps 3 per
-// SIMD.  Other buckets keep the compiler's choice (caps that spill inside
-// the insertion, k = 12 at 80, k = 16 at 96, k = 32 at 168, run up to twice
-// as long).
+// SIMD; k = 32 (split set, 24 register slots) capped at 168 measured 10%
+// faster.  Other buckets keep the compiler's choice (caps that spill inside
+// the insertion, k = 12 at 80, k = 16 at 96, k = 32 all in registers at
+// 168, run up to twice as long).
 template <int K>
 constexpr int knn_all_min_waves() {
-  return K == 10 ? 6 : (K == 12 ? 5 : (K == 20 || K == 24 ? 3 : 1));
+  return K == 10 ? 6 : (K == 12 ? 5 : (K == 20 || K == 24 || K == 32 ? 3 : 1));
 }
 
 template <int D, int K>

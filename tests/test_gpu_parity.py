@@ -90,7 +90,7 @@ def test_tree_matches_oracle(case, L):
 
 # ------------------------------------------------------- all-points rows ----
 
-@pytest.mark.parametrize("k", [1, 3, 10, 16, 18, 24, 29, 50, 64])
+@pytest.mark.parametrize("k", [1, 3, 10, 16, 18, 24, 29, 37, 50, 64])
 @pytest.mark.parametrize("case", range(len(DATA)), ids=IDS)
 def test_all_points_match_oracle(case, k):
     name, P, box = DATA[case]
@@ -133,7 +133,7 @@ def test_config1_uniform2d_full():
 
 # -------------------------------------------------------- external rows ----
 
-@pytest.mark.parametrize("k", [1, 8, 16, 20, 30, 40])
+@pytest.mark.parametrize("k", [1, 8, 16, 20, 30, 40, 45])
 @pytest.mark.parametrize("case", [0, 1, 3, 4, 7], ids=[IDS[i] for i in (0, 1, 3, 4, 7)])
 def test_external_queries_match_oracle(case, k):
     name, P, box = DATA[case]
