@@ -808,8 +808,18 @@ k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
 
 // External rows: wavefront w answers the Morton-sorted queries
 // order[64w .. 64w + 64); row r of the output belongs to query r.
+// Register budget of the external-query kernel: k = 16 capped at 128 VGPRs
+// (4 wavefronts per SIMD instead of 3) and k = 24 and 32 at 168 (3 instead
+// of 2) measured 9-12% faster; k = 40 capped at 168 ran 8% slower and keeps
+// the compiler's choice, like the other buckets.
+template <int K>
+constexpr int knn_ext_min_waves() {
+  return K == 16 ? 4 : (K == 24 || K == 32 ? 3 : 1);
+}
+
 template <int D, int K>
-__global__ void __launch_bounds__(256) k_knn_ext(TreeView t, const double *__restrict__ q,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(knn_ext_min_waves<K>())))
+k_knn_ext(TreeView t, const double *__restrict__ q,
                                                  const uint64_t *__restrict__ qkey,
                                                  const int32_t *__restrict__ order, int64_t m,
                                                  int k, int32_t *__restrict__ out_ids,
