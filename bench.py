@@ -1,7 +1,8 @@
 """Benchmark of the zd-tree k-NN hot path on one MI355X.
 
 Default workload (3D uniform, the headline configuration): n = 10,000,000
-points uniform in [0,1)^3, leaf size 16, k = 10.  One step is one pass of the
+points uniform in [0,1)^3, leaf size 24 (the fastest whole step in a sweep
+of leaf sizes 12-64), k = 10.  One step is one pass of the
 whole path over resident inputs:
 
     build(10M) -> all-points k-NN -> insert 1M -> delete 1M -> all-points k-NN
@@ -59,7 +60,8 @@ BUILD_BYTES_PER_POINT = (24 + 12) + 8 * (8 + 12 + 12) + (4 + 24 + 24 + 4) + (8 +
 # 3 sub, 3 mul, 2 add) and box tests (17 ops each) of the serial oracle's
 # leaf-based search over 200,000 evenly spaced ids, printed by
 # `python oracle/work_counters.py --leaf L`.
-WORK_PER_QUERY = {8: (59.59, 64.24), 16: (92.0, 49.21), 24: (120.42, 41.3), 32: (134.92, 38.39)}
+WORK_PER_QUERY = {8: (59.59, 64.24), 16: (92.0, 49.21), 24: (120.42, 41.3), 32: (134.92, 38.39),
+                  40: (161.18, 34.25), 48: (180.7, 31.62)}
 
 
 def ops_per_query(leaf):
@@ -78,8 +80,8 @@ PAPER_BUILD_QUERY_K10_QPS = 10_000_000 / 0.453  # CPU context only (144 threads)
 # sha1 only; after any change to that code the figure is reported as null
 # until the counters are taken again.
 KNN_TRAFFIC = {"sources_sha1": "299d149e3f17890a1b3690cbe481ef8182116b51",
-               "fetch_bytes": 2.710e9, "write_bytes": 2.350e9}
-TRAFFIC_LEAF = 16  # leaf size of the profiled run
+               "fetch_bytes": 2.233e9, "write_bytes": 2.348e9}
+TRAFFIC_LEAF = 24  # leaf size of the profiled run
 KNN_SOURCES = ("paper_2111_04182_amd/csrc/zd_knn_impl.h", "paper_2111_04182_amd/csrc/zd_internal.h",
                "paper_2111_04182_amd/csrc/zd_knn_all_d3.hip")
 
@@ -144,7 +146,7 @@ def main():
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--m", type=int, default=1_000_000)
     ap.add_argument("--k", type=int, default=10)
-    ap.add_argument("--leaf", type=int, default=16)
+    ap.add_argument("--leaf", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=500_000)
     ap.add_argument("--workload", default="uniform3d",
@@ -240,7 +242,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "3D uniform [0,1)^3 n=10M, leaf 16, k=10: build, all-points "
+        "config": {"workload": f"3D uniform [0,1)^3 n=10M, leaf {L}, k=10: build, all-points "
                                "k-NN, insert 1M, delete 1M, all-points k-NN",
                    "n": n, "k": k, "leaf_size": L, "insert": m, "delete": m},
         "build_mpts_s": n / (ph["build"] / 1e3) / 1e6,
@@ -321,7 +323,7 @@ def bench_spheres(args):
         "metric": "all-points kNN queries/s, 3D clustered spheres 10M (k=10 and k=50)",
         "value": 2 * n / (total / 1e3), "unit": "queries/s", "n_gpus": 1, "dtype": "f64",
         "data": "synthetic", "config": {"workload": "64 noisy spheres + 1% background, n=10M, "
-                                                    "leaf 16: build, k=10, k=50", "n": n},
+                                                    f"leaf {args.leaf}: build, k=10, k=50", "n": n},
         "build_mpts_s": n / res["build_ms"] / 1e3, "query_k10_qps": n / res["query_k10_ms"] * 1e3,
         "query_k50_qps": n / res["query_k50_ms"] * 1e3, "phase_ms": res}), flush=True)
 
