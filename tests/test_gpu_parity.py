@@ -264,13 +264,15 @@ def test_autograd_function():
 # ---------------------------------------------------- full-size sampled ----
 
 @pytest.mark.timeout(600)
-def test_config2_full_size_sampled():
-    """3D uniform, n = 10M: tree equals the oracle's; sampled rows equal the
-    oracle's; then insert 1M, delete 1M, re-query (sampled)."""
+@pytest.mark.parametrize("L", [16, 24])
+def test_config2_full_size_sampled(L):
+    """3D uniform, n = 10M (leaf 24 is the bench's): tree equals the oracle's;
+    sampled rows equal the oracle's; then insert 1M, delete 1M, re-query
+    (sampled)."""
     P, Q, D = W.cfg2_uniform3d()
-    print("config2: building", flush=True)
-    g = zd.ZdTree(dev(P), 16, box=W.UNIT3, shift_seed=0)
-    o = oracle.Tree(P, 16, box=W.UNIT3, seed=0)
+    print(f"config2 L={L}: building", flush=True)
+    g = zd.ZdTree(dev(P), L, box=W.UNIT3, shift_seed=0)
+    o = oracle.Tree(P, L, box=W.UNIT3, seed=0)
     gex, oex = g.export(), o.export()
     for key in ("keys", "ids", "leaf_count", "int_bit"):
         assert np.array_equal(gex[key], oex[key]), key
@@ -282,7 +284,7 @@ def test_config2_full_size_sampled():
     few = rows[:25]
     assert_same_rows((ids[torch.from_numpy(few).cuda()], d2[torch.from_numpy(few).cuda()]),
                      oracle.brute_knn(P, 10, qids=few), "config2 brute rows")
-    print("config2: updates", flush=True)
+    print(f"config2 L={L}: updates", flush=True)
     g.insert(dev(Q))
     o.insert(Q)
     g.delete(torch.from_numpy(D).cuda())
