@@ -323,12 +323,14 @@ def test_config3_spheres_scaled(k):
 
 
 @pytest.mark.timeout(900)
-def test_config3_full_size_sampled():
-    """10M sphere-surface points, k = 10 and k = 50, sampled rows."""
+@pytest.mark.parametrize("L", [16, 24])
+def test_config3_full_size_sampled(L):
+    """10M sphere-surface points, k = 10 and k = 50, sampled rows (leaf 24 is
+    the bench's)."""
     P = W.cfg3_spheres()
-    print("config3: building", flush=True)
-    g = zd.ZdTree(dev(P), 16, shift_seed=0)
-    o = oracle.Tree(P, 16, seed=0)
+    print(f"config3 L={L}: building", flush=True)
+    g = zd.ZdTree(dev(P), L, shift_seed=0)
+    o = oracle.Tree(P, L, seed=0)
     gex, oex = g.export(), o.export()
     for key in ("keys", "ids", "leaf_count", "int_bit"):
         assert np.array_equal(gex[key], oex[key]), key
