@@ -302,7 +302,7 @@ def bench_spheres(args):
     import paper_2111_04182_amd as zd
     import workloads as W
     log("bench spheres: generating 10M sphere-surface points")
-    P = W.cfg3_spheres()
+    P = W.spheres_10m()
     xyz = zd.soa(torch.from_numpy(P))
     n = P.shape[0]
     res = {}
@@ -335,7 +335,7 @@ def bench_forest(args):
     from paper_2111_04182_amd.autotune import tune_forest
     k = 16
     log("bench forest: generating 4096 clouds")
-    P, off = W.cfg4_forest()
+    P, off = W.forest_4096_clouds()
     N = P.shape[0]
     xyz = zd.soa(torch.from_numpy(P))
     log(f"bench forest: N={N}, autotuning leaf sizes and launch shape")
@@ -388,7 +388,7 @@ def bench_grad(args):
     import paper_2111_04182_amd as zd
     import workloads as W
     k = 8
-    P, fd, inserts, delete_rngs, m = W.cfg5_uniform3d()
+    P, fd, inserts, delete_rngs, m = W.uniform3d_1m_rounds()
     n0 = P.shape[0]
     pts = P.copy()
     live = np.ones(n0, dtype=bool)

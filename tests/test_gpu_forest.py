@@ -122,8 +122,8 @@ def test_forest_graph_replays():
     plan.close()
 
 
-def test_forest_config4_scaled_matches_single_trees():
-    P, off = W.cfg4_forest(n_clouds=48, seed=7)
+def test_forest_scaled_matches_single_trees():
+    P, off = W.forest_4096_clouds(n_clouds=48, seed=7)
     xyz = dev(P)
     k = 16
     f = zd.ZdForest(xyz, off, leaf_size=16)
@@ -163,11 +163,11 @@ def test_forest_argument_errors():
 
 
 @pytest.mark.timeout(900)
-def test_forest_config4_full_size_sampled():
+def test_forest_4096_clouds_full_size_sampled():
     """The full batched workload (4096 clouds, 62M points, k=16) as the bench
     runs it (captured plan, per-bucket leaf sizes): sampled rows of sampled
     clouds against the oracle's brute force over that cloud."""
-    P, off = W.cfg4_forest()
+    P, off = W.forest_4096_clouds()
     xyz = dev(P)
     k = 16
     sizes = np.diff(off)

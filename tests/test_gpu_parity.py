@@ -122,12 +122,12 @@ def test_query_waves_do_not_change_rows(waves, k):
     g.close()
 
 
-def test_config1_uniform2d_full():
-    P = W.cfg1_uniform2d()
+def test_uniform2d_10k_full():
+    P = W.uniform2d_10k()
     g = zd.ZdTree(dev(P), leaf_size=16, box=W.UNIT2, shift_seed=0)
     o = oracle.Tree(P, 16, box=W.UNIT2, seed=0)
-    assert_same_tree(g.export(), o.export(), 2, "config1")
-    assert_same_rows(g.knn(10), oracle.brute_knn(P, 10), "config1")
+    assert_same_tree(g.export(), o.export(), 2, "uniform2d 10k")
+    assert_same_rows(g.knn(10), oracle.brute_knn(P, 10), "uniform2d 10k")
     g.close()
 
 
@@ -265,12 +265,12 @@ def test_autograd_function():
 
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("L", [16, 24])
-def test_config2_full_size_sampled(L):
+def test_uniform3d_10m_full_size_sampled(L):
     """3D uniform, n = 10M (leaf 24 is the bench's): tree equals the oracle's;
     sampled rows equal the oracle's; then insert 1M, delete 1M, re-query
     (sampled)."""
-    P, Q, D = W.cfg2_uniform3d()
-    print(f"config2 L={L}: building", flush=True)
+    P, Q, D = W.uniform3d_10m_updates()
+    print(f"uniform3d 10M L={L}: building", flush=True)
     g = zd.ZdTree(dev(P), L, box=W.UNIT3, shift_seed=0)
     o = oracle.Tree(P, L, box=W.UNIT3, seed=0)
     gex, oex = g.export(), o.export()
@@ -280,11 +280,11 @@ def test_config2_full_size_sampled(L):
     rows = np.random.default_rng(5).choice(len(P), 20000, replace=False)
     want = o.knn_all(10, qids=rows)
     assert_same_rows((ids[torch.from_numpy(rows).cuda()], d2[torch.from_numpy(rows).cuda()]), want,
-                     "config2 rows")
+                     "uniform3d 10M rows")
     few = rows[:25]
     assert_same_rows((ids[torch.from_numpy(few).cuda()], d2[torch.from_numpy(few).cuda()]),
-                     oracle.brute_knn(P, 10, qids=few), "config2 brute rows")
-    print(f"config2 L={L}: updates", flush=True)
+                     oracle.brute_knn(P, 10, qids=few), "uniform3d 10M brute rows")
+    print(f"uniform3d 10M L={L}: updates", flush=True)
     g.insert(dev(Q))
     o.insert(Q)
     g.delete(torch.from_numpy(D).cuda())
@@ -297,38 +297,38 @@ def test_config2_full_size_sampled(L):
     rows = np.random.default_rng(6).choice(live, 20000, replace=False)
     want = o.knn_all(10, qids=rows)
     assert_same_rows((ids[torch.from_numpy(rows).cuda()], d2[torch.from_numpy(rows).cuda()]), want,
-                     "config2 rows after updates")
+                     "uniform3d 10M rows after updates")
     dead = D[:100]
     assert (ids[torch.from_numpy(dead).cuda()].cpu().numpy() == -1).all()
     g.close()
 
 
 @pytest.mark.parametrize("k", [10, 50])
-def test_config3_spheres_scaled(k):
+def test_spheres_scaled(k):
     """Points on 64 noisy sphere surfaces plus uniform background (the
     sphere-surface workload at 1/25 scale): full rows against brute force on a
     sample, and against the oracle's own tree search on a larger sample."""
-    P = W.cfg3_spheres(n=400_000)
+    P = W.spheres_10m(n=400_000)
     g = zd.ZdTree(dev(P), 16, shift_seed=2)
     ids, d2 = g.knn(k)
     rows = np.random.default_rng(k).choice(len(P), 4000, replace=False)
     sel = torch.from_numpy(rows).cuda()
     o = oracle.Tree(P, 16, seed=2)
-    assert_same_tree(g.export(), o.export(), 3, "config3 tree")
-    assert_same_rows((ids[sel], d2[sel]), o.knn_all(k, qids=rows), f"config3 k={k}")
+    assert_same_tree(g.export(), o.export(), 3, "spheres tree")
+    assert_same_rows((ids[sel], d2[sel]), o.knn_all(k, qids=rows), f"spheres k={k}")
     few = rows[:40]
     sel = torch.from_numpy(few).cuda()
-    assert_same_rows((ids[sel], d2[sel]), oracle.brute_knn(P, k, qids=few), f"config3 brute k={k}")
+    assert_same_rows((ids[sel], d2[sel]), oracle.brute_knn(P, k, qids=few), f"spheres brute k={k}")
     g.close()
 
 
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("L", [16, 24])
-def test_config3_full_size_sampled(L):
+def test_spheres_10m_full_size_sampled(L):
     """10M sphere-surface points, k = 10 and k = 50, sampled rows (leaf 24 is
     the bench's)."""
-    P = W.cfg3_spheres()
-    print(f"config3 L={L}: building", flush=True)
+    P = W.spheres_10m()
+    print(f"spheres 10M L={L}: building", flush=True)
     g = zd.ZdTree(dev(P), L, shift_seed=0)
     o = oracle.Tree(P, L, seed=0)
     gex, oex = g.export(), o.export()
@@ -338,7 +338,7 @@ def test_config3_full_size_sampled(L):
     sel = torch.from_numpy(rows).cuda()
     for k in (10, 50):
         ids, d2 = g.knn(k)
-        assert_same_rows((ids[sel], d2[sel]), o.knn_all(k, qids=rows), f"config3 10M k={k}")
+        assert_same_rows((ids[sel], d2[sel]), o.knn_all(k, qids=rows), f"spheres 10M k={k}")
         del ids, d2
     g.close()
 

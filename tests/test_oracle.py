@@ -284,8 +284,8 @@ def test_search_work_is_bounded():
     assert per[1] < 1.5 * per[0] and per[1] < 400
 
 
-def test_config1_full_matches_brute_force():
-    P = W.cfg1_uniform2d()
+def test_uniform2d_10k_full_matches_brute_force():
+    P = W.uniform2d_10k()
     t = oracle.Tree(P, 16, box=W.UNIT2)
     a = t.knn_all(10)
     b = oracle.brute_knn(P, 10)

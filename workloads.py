@@ -22,14 +22,14 @@ def uniform(n: int, dim: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).random((n, dim))
 
 
-# -- the five workload configurations ---------------------------------------
+# -- the benchmark workloads --------------------------------------------------
 
-def cfg1_uniform2d(n: int = 10_000, seed: int = 0) -> np.ndarray:
+def uniform2d_10k(n: int = 10_000, seed: int = 0) -> np.ndarray:
     """2D uniform in [0,1)^2, leaf size 16, all-points k=10."""
     return uniform(n, 2, seed)
 
 
-def cfg2_uniform3d(n: int = 10_000_000, m: int = 1_000_000):
+def uniform3d_10m_updates(n: int = 10_000_000, m: int = 1_000_000):
     """3D uniform build set P (seed 0), insert batch Q (seed 1, ids n..n+m-1),
     delete ids D: m distinct ids drawn from all n+m after the insert (seed 2)."""
     P = uniform(n, 3, 0)
@@ -38,7 +38,7 @@ def cfg2_uniform3d(n: int = 10_000_000, m: int = 1_000_000):
     return P, Q, D
 
 
-def cfg3_spheres(n: int = 10_000_000, n_spheres: int = 64, noise: float = 1e-4,
+def spheres_10m(n: int = 10_000_000, n_spheres: int = 64, noise: float = 1e-4,
                  background: float = 0.01, seed: int = 0) -> np.ndarray:
     """Points on n_spheres sphere surfaces (radius log-uniform in [0.01, 0.2],
     centres uniform in [0,1)^3) with Gaussian radial noise, plus a uniform
@@ -58,7 +58,7 @@ def cfg3_spheres(n: int = 10_000_000, n_spheres: int = 64, noise: float = 1e-4,
     return allp[rng.permutation(n)]
 
 
-def cfg4_forest(n_clouds: int = 4096, min_size: int = 1000, max_size: int = 65536,
+def forest_4096_clouds(n_clouds: int = 4096, min_size: int = 1000, max_size: int = 65536,
                 seed: int = 0):
     """Independent 3D clouds, sizes log-uniform in [min_size, max_size], each a
     Gaussian mixture of 1..8 equal-weight components (sigma in [0.02, 0.1],
@@ -79,7 +79,7 @@ def cfg4_forest(n_clouds: int = 4096, min_size: int = 1000, max_size: int = 6553
     return out, offsets
 
 
-def cfg5_uniform3d(n: int = 1_000_000, rounds: int = 10, frac: float = 0.01,
+def uniform3d_1m_rounds(n: int = 1_000_000, rounds: int = 10, frac: float = 0.01,
                    n_fd: int = 1000):
     """Differentiable workload: P (seed 0); finite-difference sample of
     (point id, coordinate) pairs (seed 1); per round r = 1..rounds an insert
