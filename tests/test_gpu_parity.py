@@ -303,6 +303,25 @@ def test_uniform3d_10m_full_size_sampled(L):
     g.close()
 
 
+@pytest.mark.timeout(600)
+def test_uniform3d_10m_external_sampled():
+    """1M external queries (inside and slightly outside the box) against a
+    10M-point tree at the bench's leaf size: sampled rows against the
+    oracle's bit-based search and a few against brute force."""
+    P = W.uniform(10_000_000, 3, 0)
+    Q = W.uniform(1_000_000, 3, 7) * 1.02 - 0.01
+    g = zd.ZdTree(dev(P), 24, box=W.UNIT3, shift_seed=0)
+    o = oracle.Tree(P, 24, box=W.UNIT3, seed=0)
+    ids, d2 = g.knn(10, dev(Q))
+    rows = np.random.default_rng(8).choice(len(Q), 2000, replace=False)
+    sel = torch.from_numpy(rows).cuda()
+    assert_same_rows((ids[sel], d2[sel]), o.knn(Q[rows], 10), "external 1M rows")
+    few = rows[:20]
+    assert_same_rows((ids[torch.from_numpy(few).cuda()], d2[torch.from_numpy(few).cuda()]),
+                     oracle.brute_knn(P, 10, queries=Q[few]), "external 1M brute rows")
+    g.close()
+
+
 @pytest.mark.parametrize("k", [10, 50])
 def test_spheres_scaled(k):
     """Points on 64 noisy sphere surfaces plus uniform background (the
