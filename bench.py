@@ -83,7 +83,7 @@ KNN_TRAFFIC = {"sources_sha1": "299d149e3f17890a1b3690cbe481ef8182116b51",
                "fetch_bytes": 2.233e9, "write_bytes": 2.348e9}
 TRAFFIC_LEAF = 24  # leaf size of the profiled run
 KNN_SOURCES = ("paper_2111_04182_amd/csrc/zd_knn_impl.h", "paper_2111_04182_amd/csrc/zd_internal.h",
-               "paper_2111_04182_amd/csrc/zd_knn_all_d3.hip")
+               "paper_2111_04182_amd/csrc/zd_sortnet.h", "paper_2111_04182_amd/csrc/zd_knn_all_d3.hip")
 
 
 def sources_sha1(paths):

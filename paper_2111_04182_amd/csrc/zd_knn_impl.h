@@ -29,8 +29,10 @@
 #pragma once
 
 #include "zd_internal.h"
+#include "zd_sortnet.h"
 
 #include <climits>
+#include <utility>
 
 namespace zd {
 
@@ -192,6 +194,28 @@ struct Heap {
         id[0] = q;
       }
     }
+  }
+
+  // An empty set (k = K) that takes K candidates in a row ends up holding
+  // them in ascending (d2, id) order.  The caller stores them unsorted in
+  // the K slots and sorts them with a merge network: a compare-exchange
+  // per comparator (32 for K = 10) instead of K full insertion shifts.
+  template <int A, int B>
+  __device__ __forceinline__ void cmp_ex() {
+    const bool sw = cand_lt(d[B], id[B], d[A], id[A]);
+    const double x = d[A], y = d[B];
+    const int32_t i = id[A], j = id[B];
+    d[A] = sw ? y : x;
+    d[B] = sw ? x : y;
+    id[A] = sw ? j : i;
+    id[B] = sw ? i : j;
+  }
+  template <int... I>
+  __device__ __forceinline__ void run_net(std::integer_sequence<int, I...>) {
+    (cmp_ex<SortNetFor<K>::net.v[I].lo, SortNetFor<K>::net.v[I].hi>(), ...);
+  }
+  __device__ __forceinline__ void sort_slots() {
+    run_net(std::make_integer_sequence<int, SortNetFor<K>::net.n>{});
   }
 
   __device__ __forceinline__ void write(int k, int32_t *out_ids, double *out_d2) const {
@@ -418,14 +442,18 @@ struct SplitSet {
   }
 };
 
-// Per k bucket: the candidate set, its per-lane LDS slots, and whether the
+// Per k bucket: the candidate set, its per-lane LDS slots, whether the
 // prescore runs in the shared order over a 64-entry stage (the LDS heap)
-// or each lane's near-first order over the whole window.
+// or each lane's near-first order over the whole window, and whether the
+// set is filled by a sorting network (the register sets; not k = 12, where
+// the fill adds two spilled dwords under the 96-VGPR cap and the query
+// measured 20% slower, while k = 8-24 otherwise gain 1-3%).
 template <int K>
 struct HeapFor {
   using type = Heap<K>;
   static constexpr int lds_slots = 0;
   static constexpr bool shared_prescore = false;
+  static constexpr bool sorted_fill = K != 12;
 };
 #define ZD_SPLIT_SET(KK, RR)                       \
   template <>                                      \
@@ -433,6 +461,7 @@ struct HeapFor {
     using type = SplitSet<KK, RR>;                 \
     static constexpr int lds_slots = KK - RR;      \
     static constexpr bool shared_prescore = false; \
+    static constexpr bool sorted_fill = false;     \
   };
 ZD_SPLIT_SET(32, 24)
 ZD_SPLIT_SET(40, 24)
@@ -443,6 +472,7 @@ struct HeapFor<64> {
   using type = LdsHeap<64>;
   static constexpr int lds_slots = 64;
   static constexpr bool shared_prescore = true;
+  static constexpr bool sorted_fill = false;
 };
 
 // withinBox(C, p, -r) of Algorithm 3, squared: p in the box and every face
@@ -542,7 +572,11 @@ struct WaveSearch {
   // Morton neighbours first and every other position of [a, b] exactly
   // once.  Its k-th distance tightens sooner than in the shared order, and
   // fewer later candidates enter.  The stage holds the whole window.
-  __device__ __forceinline__ void prescore_near_first(int64_t a, int64_t b, int64_t own) {
+  // For the register sets, the first min(k, cnt - 1) steps fill the empty
+  // set without insertions: each lane stores those candidates in its slots
+  // and sorts them (Heap::sort_slots), which leaves the set as that many
+  // insertions would.
+  __device__ __forceinline__ void prescore_near_first(int64_t a, int64_t b, int64_t own, int k) {
     const int lane = threadIdx.x & 63;
     const int cnt = (int)(b - a + 1);  // <= 64 + 2 kPrescore entries of the stage
     for (int j = lane; j < cnt; j += 64) {
@@ -556,7 +590,30 @@ struct WaveSearch {
     }
     __builtin_amdgcn_wave_barrier();
     const int o = valid ? (int)(own - a) : 0;
-    for (int s = 1; s < cnt; ++s) {
+    int s0 = 1;
+    if constexpr (HeapFor<K>::sorted_fill) {
+      // f = min(k, cnt - 1) candidates: slot s - 1 takes step s's candidate
+      // for s <= f, an empty entry (+inf, INT_MAX) for f < s <= k and the
+      // padding (-inf, INT_MIN) for s > k.  Sorted, the slots hold what
+      // init and f insertions leave: the padding, the candidates ascending,
+      // then the empty entries.  (Ids are distinct, so the order is total.)
+      const int f = min(k, cnt - 1);
+#pragma unroll
+      for (int s = 1; s <= K; ++s) {
+        const int m = (s + 1) >> 1;
+        int j = (s & 1) ? o + m : o - m;
+        j = j >= cnt ? j - cnt : (j < 0 ? j + cnt : j);
+        const Cand q = stage[s <= f ? j : 0];
+        const double dd = dist2<D>(px, py, pz, q.x, q.y, q.z);
+        if (valid) {
+          h.d[s - 1] = s <= f ? dd : (s <= k ? INFINITY : -INFINITY);
+          h.id[s - 1] = s <= f ? q.id : (s <= k ? INT_MAX : INT_MIN);
+        }
+      }
+      h.sort_slots();
+      s0 = f + 1;
+    }
+    for (int s = s0; s < cnt; ++s) {
       const int m = (s + 1) >> 1;
       int j = (s & 1) ? o + m : o - m;
       j = j >= cnt ? j - cnt : (j < 0 ? j + cnt : j);
@@ -789,7 +846,7 @@ k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
   if constexpr (HeapFor<K>::shared_prescore)
     s.prescore(max(c_lo, g0 - kPrescore), min(c_hi, last + kPrescore), g0 + lane);
   else
-    s.prescore_near_first(max(c_lo, g0 - kPrescore), min(c_hi, last + kPrescore), g0 + lane);
+    s.prescore_near_first(max(c_lo, g0 - kPrescore), min(c_hi, last + kPrescore), g0 + lane, k);
   // lowest common ancestor of the group's leaves
   const int32_t lf = uni(t.leaf_of[g0]), ll = uni(t.leaf_of[last]);
   int32_t G = ~lf;
