@@ -25,6 +25,14 @@
  *     runtime when an allocation fails (and at process exit).
  *   - Errors are returned before anything is enqueued; out-parameters are
  *     untouched on error.  No C++ exception crosses this interface.
+ *   - Self-checks: the build counts any inconsistency of its bottom-up climb,
+ *     and a search that stops before it has finished (a corrupted tree, or
+ *     the step limit of zd_set_walk_limit) counts itself; both counts live
+ *     on the device.  Every call that synchronises the tree's stream
+ *     (zd_info, zd_export, zd_check, the updates) reads them, and if either
+ *     is non-zero returns ZD_EDEVICE and marks the tree broken: its rows
+ *     since the last check cannot be trusted, and only zd_free remains
+ *     valid.
  *   - Squared distances d2(a,b) = ((dx*dx + dy*dy) + dz*dz), dx = a.x - b.x,
  *     binary64 with no fused multiply-add.  Neighbours are ordered by
  *     (d2, id) ascending; equal d2 goes to the lower id.  Results are exact:
@@ -99,7 +107,8 @@ typedef struct {
  * Asynchronous on `stream` when a box is given; with box_lo == NULL the call
  * synchronises `stream` once to read the data's bounding cube.
  * Errors: ZD_EINVAL for a NULL params/out, dim not 2 or 3, leaf_size < 1,
- * n < 0, n > 2^31 - 2, a NULL xyz with n > 0, n == 0 without a box, only one
+ * n < 0, n > 2^30 - 1 (node links are (node << 1) | side in int32, and a
+ * tree of n points has up to n - 1 internal nodes), a NULL xyz with n > 0, n == 0 without a box, only one
  * of box_lo / box_hi given, hi <= lo, a non-finite box, a shift value out
  * of range, or query_waves not 0, 1, 2 or 4; ZD_ENOMEM; ZD_EDEVICE. */
 ZD_API zd_status zd_build(const zd_params *params, const double *xyz, int64_t n,
@@ -118,9 +127,14 @@ ZD_API zd_status zd_build(const zd_params *params, const double *xyz, int64_t n,
  *   out_ids: (device) [m][k] int32 neighbour ids, out_d2: (device) [m][k]
  *     FP64 squared distances; each row ascending by (d2, id); a row with
  *     fewer than k candidates is padded with (-1, +inf).
- * Asynchronous.  Concurrent zd_knn calls on one tree are safe.
- * Errors: ZD_EINVAL (NULL tree or outputs, m < 0, k < 1, m mismatch),
- * ZD_EKMAX (k > ZD_KMAX), ZD_ENOMEM, ZD_EDEVICE. */
+ * Asynchronous.  A query only reads the tree: concurrent zd_knn calls on one
+ * tree, from several host threads and on several streams, are safe.  A
+ * query on a stream other than the tree's own is ordered after the tree's
+ * pending work, and the tree's later work (updates, zd_free) after the
+ * query, by events; the tree itself is not changed.
+ * Errors: ZD_EINVAL (NULL tree or outputs, m < 0, k < 1, m mismatch,
+ * m > 2^30 - 1 external queries), ZD_EKMAX (k > ZD_KMAX), ZD_ENOMEM,
+ * ZD_EDEVICE (a broken tree, or a HIP failure). */
 ZD_API zd_status zd_knn(zd_tree tree, const double *q_xyz, int64_t m, int32_t k,
                  int32_t *out_ids, double *out_d2, void *stream);
 
@@ -130,8 +144,10 @@ ZD_API zd_status zd_knn(zd_tree tree, const double *q_xyz, int64_t m, int32_t k,
  * The batch is all-or-nothing: if any point lies outside the declared box
  * the call returns ZD_EBOUNDS and the tree is unchanged.  Afterwards the tree
  * equals a fresh build of the live points (same box and shift).
- * Synchronises `stream` (to validate the batch).
- * Errors: ZD_EINVAL, ZD_EBOUNDS, ZD_ENOMEM, ZD_EDEVICE. */
+ * Synchronises `stream` (to validate the batch).  Updates need exclusive
+ * access to the tree.
+ * Errors: ZD_EINVAL (also when the live points would exceed 2^30 - 1 or the
+ * id capacity 2^31 - 2), ZD_EBOUNDS, ZD_ENOMEM, ZD_EDEVICE. */
 ZD_API zd_status zd_insert_batch(zd_tree tree, const double *xyz, int64_t m,
                           int32_t *out_new_ids, void *stream);
 
@@ -150,10 +166,25 @@ ZD_API zd_status zd_delete_batch(zd_tree tree, const int32_t *ids, int64_t m,
 ZD_API zd_status zd_free(zd_tree tree);
 
 /* Sizes of a tree: live points, id capacity (rows of an all-points query),
- * leaves, internal nodes.  Any pointer may be NULL.  Synchronises the tree's
- * stream. */
+ * leaves, internal nodes, and depth (the most edges from the root to a leaf;
+ * Theorem 1 bounds it by O(log n) on data of bounded aspect ratio; computed
+ * on the device only when `depth` is non-NULL).  Any pointer may be NULL.
+ * Synchronises the tree's stream and runs the self-checks.
+ * Errors: ZD_EINVAL (NULL tree), ZD_EDEVICE (a self-check failed, or HIP). */
 ZD_API zd_status zd_info(zd_tree tree, int64_t *n_live, int64_t *id_capacity,
-                  int64_t *n_leaves, int64_t *n_internal);
+                  int64_t *n_leaves, int64_t *n_internal, int32_t *depth);
+
+/* Synchronise the tree's stream and run the self-checks: ZD_OK, or
+ * ZD_EDEVICE when the build or a search since the last check found the tree
+ * inconsistent (the tree is then broken).  ZD_EINVAL for a NULL tree. */
+ZD_API zd_status zd_check(zd_tree tree);
+
+/* Test hook: bound every later search of this tree to `steps` walk steps
+ * (node and climb steps; 0 restores the default of 4n + 256, which a valid
+ * tree never reaches).  A search that reaches the bound stops early, its row
+ * is not exact, and the next zd_check (or other synchronising call) reports
+ * ZD_EDEVICE.  Errors: ZD_EINVAL (NULL tree, steps < 0). */
+ZD_API zd_status zd_set_walk_limit(zd_tree tree, int64_t steps);
 
 /* Copy the tree to caller-owned host arrays in its canonical in-order form
  * (for tests): the live (key, id) pairs in Morton order, every leaf's size
@@ -217,6 +248,10 @@ ZD_API zd_status zd_forest_plan(const zd_params *params, const double *xyz, int6
                                 const int32_t *leaf_sizes, int32_t k, int32_t *out_ids,
                                 double *out_d2, void *stream, zd_forest *out);
 ZD_API zd_status zd_forest_run(zd_forest forest, void *stream);
+
+/* Synchronise the forest's stream and run the self-checks of its build and
+ * searches (as zd_check).  Errors: ZD_EINVAL (NULL), ZD_EDEVICE. */
+ZD_API zd_status zd_forest_check(zd_forest forest);
 
 /* Release a forest (after its work on the last stream used; a plan's graph
  * and scratch are released after synchronising that stream). */

@@ -58,12 +58,9 @@ def _load():
         lib.zo_free.argtypes = [vp]
         lib.zo_brute_knn.restype = i32
         lib.zo_brute_knn.argtypes = [i32, dp, i64, dp, i64, dp, dp, i64, i32, dp, dp]
-        lib.zo_knn_rows.restype = i32
-        lib.zo_knn_rows.argtypes = [vp, dp, i64, i32, dp, dp]
-        lib.zo_knn_root.restype = i32
-        lib.zo_knn_root.argtypes = [vp, dp, i64, i32, dp, dp]
-        lib.zo_knn_ext.restype = i32
-        lib.zo_knn_ext.argtypes = [vp, dp, i64, i32, dp, dp]
+        for fn in ("zo_knn_rows_work", "zo_knn_root_work", "zo_knn_ext_work"):
+            getattr(lib, fn).restype = i32
+            getattr(lib, fn).argtypes = [vp, dp, i64, i32, dp, dp, dp, dp]
         lib.zo_insert.restype = i32
         lib.zo_insert.argtypes = [vp, dp, i64, dp]
         lib.zo_delete.restype = i32
@@ -211,34 +208,33 @@ class Tree:
         return dict(n_live=int(v[0][0]), cap=int(v[1][0]), n_leaves=int(v[2][0]),
                     n_internal=int(v[3][0]), depth=int(dep[0]))
 
-    def knn_all(self, k, qids=None):
-        """Leaf-based rows (searchUp from each point's own leaf)."""
+    def _rows(self, fn, k, qids, work):
         cap = self.info()["cap"]
         qi = None if qids is None else np.ascontiguousarray(qids, dtype=np.int64)
         m = cap if qi is None else qi.shape[0]
+        return self._run(fn, _p(qi), m, k, work)
+
+    def _run(self, fn, src, m, k, work):
         ids = np.empty((m, k), dtype=np.int32)
         d2 = np.empty((m, k), dtype=np.float64)
-        _check(_load().zo_knn_rows(self._h, _p(qi), m, k, _p(ids), _p(d2)))
-        return ids, d2
+        wc = np.zeros(m, dtype=np.int64) if work else None
+        wb = np.zeros(m, dtype=np.int64) if work else None
+        _check(getattr(_load(), fn)(self._h, src, m, k, _p(ids), _p(d2), _p(wc), _p(wb)))
+        return (ids, d2, wc, wb) if work else (ids, d2)
 
-    def knn_root(self, k, qids=None):
+    def knn_all(self, k, qids=None, work=False):
+        """Leaf-based rows (searchUp from each point's own leaf).  With
+        work=True also the candidates scored and boxes tested per row."""
+        return self._rows("zo_knn_rows_work", k, qids, work)
+
+    def knn_root(self, k, qids=None, work=False):
         """Root-based rows (searchDown from the root)."""
-        cap = self.info()["cap"]
-        qi = None if qids is None else np.ascontiguousarray(qids, dtype=np.int64)
-        m = cap if qi is None else qi.shape[0]
-        ids = np.empty((m, k), dtype=np.int32)
-        d2 = np.empty((m, k), dtype=np.float64)
-        _check(_load().zo_knn_root(self._h, _p(qi), m, k, _p(ids), _p(d2)))
-        return ids, d2
+        return self._rows("zo_knn_root_work", k, qids, work)
 
-    def knn(self, queries, k):
+    def knn(self, queries, k, work=False):
         """Bit-based dynamic queries."""
         q = _soa(queries)
-        m = q.shape[1]
-        ids = np.empty((m, k), dtype=np.int32)
-        d2 = np.empty((m, k), dtype=np.float64)
-        _check(_load().zo_knn_ext(self._h, _p(q), m, k, _p(ids), _p(d2)))
-        return ids, d2
+        return self._run("zo_knn_ext_work", _p(q), q.shape[1], k, work)
 
     def counters(self):
         v = [np.zeros(1, dtype=np.int64) for _ in range(3)]

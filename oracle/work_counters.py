@@ -6,7 +6,8 @@ per query, C candidate distances (8 FP64 operations each: 3 subtractions,
 paper's leaf-based search (Algorithms 2 and 3), as the serial oracle performs
 them on the same tree.  This script builds the oracle tree of a workload,
 runs the leaf-based search for an evenly spaced sample of ids and prints the
-mean counts as one JSON line.
+mean and 99th-percentile counts per query, the tree's node counts and depth
+and its leaf-size histogram as one JSON line.
 
     python oracle/work_counters.py --n 10000000 --leaf 16 --k 10 --sample 200000
 
@@ -34,17 +35,21 @@ def main():
     a = ap.parse_args()
     P = W.uniform(a.n, 3, 0)
     t = oracle.Tree(P, a.leaf, box=(np.zeros(3), np.ones(3)), seed=0)
-    c0 = t.counters()
     qids = np.arange(0, a.n, max(1, a.n // a.sample))[: a.sample]
-    t.knn_all(a.k, qids=qids)
-    c1 = t.counters()
-    rows = c1["rows"] - c0["rows"]
-    cand = (c1["candidates"] - c0["candidates"]) / rows
-    box = (c1["box_tests"] - c0["box_tests"]) / rows
+    _, _, cand, box = t.knn_all(a.k, qids=qids, work=True)
+    info = t.info()
+    sizes = t.export()["leaf_count"]
+    hist = np.bincount(sizes)
     print(json.dumps({"workload": f"3D uniform n={a.n}, seed 0, box [0,1]^3", "leaf": a.leaf,
-                      "k": a.k, "queries": int(rows), "candidates_per_query": round(cand, 2),
-                      "box_tests_per_query": round(box, 2),
-                      "fp64_ops_per_query": round(8 * cand + 17 * box, 1)}))
+                      "k": a.k, "queries": int(len(qids)),
+                      "candidates_per_query": round(float(cand.mean()), 2),
+                      "candidates_p99": int(np.percentile(cand, 99)),
+                      "box_tests_per_query": round(float(box.mean()), 2),
+                      "box_tests_p99": int(np.percentile(box, 99)),
+                      "fp64_ops_per_query": round(8 * float(cand.mean()) + 17 * float(box.mean()), 1),
+                      "n_leaves": info["n_leaves"], "n_internal": info["n_internal"],
+                      "depth": info["depth"], "mean_leaf_size": round(float(sizes.mean()), 2),
+                      "leaf_size_hist": {int(s_): int(c) for s_, c in enumerate(hist) if c}}))
     t.close()
 
 

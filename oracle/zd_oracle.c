@@ -577,11 +577,21 @@ static uint64_t key_of_id(const ztree *T, int64_t id) {
   return point_key(T->dim, x, T->lo, T->S, T->shift);
 }
 
+/* Per-row work of the searches below: when row_cand / row_box are given,
+ * row r receives the candidates scored and the boxes tested for its query
+ * (test and measurement instrumentation; the search itself is unchanged). */
+static void note_work(const ztree *T, int64_t r, int64_t c0, int64_t b0, int64_t *row_cand,
+                      int64_t *row_box) {
+  if (row_cand) row_cand[r] = T->cnt_cand - c0;
+  if (row_box) row_box[r] = T->cnt_box - b0;
+}
+
 /* Leaf-based all-points rows (Section 2, "Upward search algorithm"): for
  * every id in qids (NULL: every id < cap) run searchUp from its own leaf.
  * Rows of dead ids are padded. */
-ZO_API int zo_knn_rows(void *h, const int64_t *qids, int64_t m, int k,
-                       int32_t *out_ids, double *out_d2) {
+ZO_API int zo_knn_rows_work(void *h, const int64_t *qids, int64_t m, int k,
+                            int32_t *out_ids, double *out_d2, int64_t *row_cand,
+                            int64_t *row_box) {
   ztree *T = (ztree *)h;
   if (k < 1 || m < 0) return ZO_EINVAL;
   nset N;
@@ -592,6 +602,7 @@ ZO_API int zo_knn_rows(void *h, const int64_t *qids, int64_t m, int k,
   T->cnt_cand = T->cnt_box = T->cnt_rows = 0;
   for (int64_t r = 0; r < m; ++r) {
     int64_t id = qids ? qids[r] : r;
+    const int64_t c0 = T->cnt_cand, b0 = T->cnt_box;
     N.size = 0;
     if (id >= 0 && id < T->cap && T->live[id] && T->root) {
       double p[3] = {0, 0, 0};
@@ -600,6 +611,7 @@ ZO_API int zo_knn_rows(void *h, const int64_t *qids, int64_t m, int k,
       search_up(T, C, p, id, &N);
       T->cnt_rows++;
     }
+    note_work(T, r, c0, b0, row_cand, row_box);
     nset_emit(&N, out_ids + r * k, out_d2 + r * k);
   }
   free(N.d2);
@@ -607,11 +619,17 @@ ZO_API int zo_knn_rows(void *h, const int64_t *qids, int64_t m, int k,
   return ZO_OK;
 }
 
+ZO_API int zo_knn_rows(void *h, const int64_t *qids, int64_t m, int k,
+                       int32_t *out_ids, double *out_d2) {
+  return zo_knn_rows_work(h, qids, m, k, out_ids, out_d2, NULL, NULL);
+}
+
 /* Bit-based dynamic queries (Section 2): key the query with the tree's box
  * and shift (clamped), descend by the node bits to a leaf, run searchUp with
  * nothing excluded. */
-ZO_API int zo_knn_ext(void *h, const double *q, int64_t m, int k,
-                      int32_t *out_ids, double *out_d2) {
+ZO_API int zo_knn_ext_work(void *h, const double *q, int64_t m, int k,
+                           int32_t *out_ids, double *out_d2, int64_t *row_cand,
+                           int64_t *row_box) {
   ztree *T = (ztree *)h;
   if (k < 1 || m < 0) return ZO_EINVAL;
   nset N;
@@ -623,12 +641,14 @@ ZO_API int zo_knn_ext(void *h, const double *q, int64_t m, int k,
   for (int64_t r = 0; r < m; ++r) {
     double p[3] = {0, 0, 0};
     for (int c = 0; c < T->dim; ++c) p[c] = q[c * m + r];
+    const int64_t c0 = T->cnt_cand, b0 = T->cnt_box;
     N.size = 0;
     if (T->root) {
       const node *C = leaf_of_key(T->root, point_key(T->dim, p, T->lo, T->S, T->shift));
       search_up(T, C, p, -1, &N);
     }
     T->cnt_rows++;
+    note_work(T, r, c0, b0, row_cand, row_box);
     nset_emit(&N, out_ids + r * k, out_d2 + r * k);
   }
   free(N.d2);
@@ -636,9 +656,15 @@ ZO_API int zo_knn_ext(void *h, const double *q, int64_t m, int k,
   return ZO_OK;
 }
 
+ZO_API int zo_knn_ext(void *h, const double *q, int64_t m, int k,
+                      int32_t *out_ids, double *out_d2) {
+  return zo_knn_ext_work(h, q, m, k, out_ids, out_d2, NULL, NULL);
+}
+
 /* Root-based rows (Section 2): searchDown from the root with empty N. */
-ZO_API int zo_knn_root(void *h, const int64_t *qids, int64_t m, int k,
-                       int32_t *out_ids, double *out_d2) {
+ZO_API int zo_knn_root_work(void *h, const int64_t *qids, int64_t m, int k,
+                            int32_t *out_ids, double *out_d2, int64_t *row_cand,
+                            int64_t *row_box) {
   ztree *T = (ztree *)h;
   if (k < 1 || m < 0) return ZO_EINVAL;
   nset N;
@@ -646,14 +672,18 @@ ZO_API int zo_knn_root(void *h, const int64_t *qids, int64_t m, int k,
   N.d2 = (double *)malloc(sizeof(double) * (size_t)k);
   N.id = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
   if (!N.d2 || !N.id) { free(N.d2); free(N.id); return ZO_ENOMEM; }
+  T->cnt_cand = T->cnt_box = T->cnt_rows = 0;
   for (int64_t r = 0; r < m; ++r) {
     int64_t id = qids ? qids[r] : r;
+    const int64_t c0 = T->cnt_cand, b0 = T->cnt_box;
     N.size = 0;
     if (id >= 0 && id < T->cap && T->live[id] && T->root) {
       double p[3] = {0, 0, 0};
       for (int c = 0; c < T->dim; ++c) p[c] = T->x[c][id];
       search_down(T, T->root, p, id, &N);
+      T->cnt_rows++;
     }
+    note_work(T, r, c0, b0, row_cand, row_box);
     nset_emit(&N, out_ids + r * k, out_d2 + r * k);
   }
   free(N.d2);
@@ -661,7 +691,12 @@ ZO_API int zo_knn_root(void *h, const int64_t *qids, int64_t m, int k,
   return ZO_OK;
 }
 
-/* candidates evaluated, box tests and rows of the last leaf/bit query call */
+ZO_API int zo_knn_root(void *h, const int64_t *qids, int64_t m, int k,
+                       int32_t *out_ids, double *out_d2) {
+  return zo_knn_root_work(h, qids, m, k, out_ids, out_d2, NULL, NULL);
+}
+
+/* candidates evaluated, box tests and rows of the last query call */
 ZO_API void zo_counters(void *h, int64_t *cand, int64_t *box, int64_t *rows) {
   ztree *T = (ztree *)h;
   *cand = T->cnt_cand;

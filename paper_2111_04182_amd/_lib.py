@@ -21,8 +21,8 @@ ZD_OK, ZD_EINVAL, ZD_EBOUNDS, ZD_EID, ZD_ENOMEM, ZD_EDEVICE, ZD_EKMAX = range(7)
 ZD_KMAX = 64
 
 EXPORTED = ("zd_build", "zd_knn", "zd_insert_batch", "zd_delete_batch", "zd_free", "zd_info",
-            "zd_export", "zd_knn_backward", "zd_forest_build", "zd_forest_knn", "zd_forest_plan",
-            "zd_forest_run", "zd_forest_free", "zd_status_str")
+            "zd_check", "zd_set_walk_limit", "zd_export", "zd_knn_backward", "zd_forest_build", "zd_forest_knn", "zd_forest_plan",
+            "zd_forest_run", "zd_forest_check", "zd_forest_free", "zd_status_str")
 
 
 class ZdError(RuntimeError):
@@ -63,7 +63,11 @@ def lib() -> C.CDLL:
         L.zd_free.restype = C.c_int
         L.zd_free.argtypes = [vp]
         L.zd_info.restype = C.c_int
-        L.zd_info.argtypes = [vp, vp, vp, vp, vp]
+        L.zd_info.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.zd_check.restype = C.c_int
+        L.zd_check.argtypes = [vp]
+        L.zd_set_walk_limit.restype = C.c_int
+        L.zd_set_walk_limit.argtypes = [vp, i64]
         L.zd_export.restype = C.c_int
         L.zd_export.argtypes = [vp] * 11
         L.zd_knn_backward.restype = C.c_int
@@ -77,6 +81,8 @@ def lib() -> C.CDLL:
                                      C.POINTER(vp)]
         L.zd_forest_run.restype = C.c_int
         L.zd_forest_run.argtypes = [vp, vp]
+        L.zd_forest_check.restype = C.c_int
+        L.zd_forest_check.argtypes = [vp]
         L.zd_forest_free.restype = C.c_int
         L.zd_forest_free.argtypes = [vp]
         _lib = L
@@ -172,10 +178,23 @@ def zd_free(tree):
         _check(lib().zd_free(tree), "zd_free")
 
 
-def zd_info(tree) -> dict:
+def zd_info(tree, depth: bool = False) -> dict:
     v = [C.c_int64() for _ in range(4)]
-    _check(lib().zd_info(tree, *[C.byref(x) for x in v]), "zd_info")
-    return dict(n_live=v[0].value, cap=v[1].value, n_leaves=v[2].value, n_internal=v[3].value)
+    d = C.c_int32()
+    _check(lib().zd_info(tree, *[C.byref(x) for x in v], C.byref(d) if depth else None),
+           "zd_info")
+    out = dict(n_live=v[0].value, cap=v[1].value, n_leaves=v[2].value, n_internal=v[3].value)
+    if depth:
+        out["depth"] = d.value
+    return out
+
+
+def zd_check(tree):
+    _check(lib().zd_check(tree), "zd_check")
+
+
+def zd_set_walk_limit(tree, steps: int):
+    _check(lib().zd_set_walk_limit(tree, steps), "zd_set_walk_limit")
 
 
 def zd_export(tree, dim: int) -> dict:
@@ -227,8 +246,11 @@ class ZdTree:
     def handle(self):
         return self._h
 
-    def info(self) -> dict:
-        return zd_info(self._h)
+    def info(self, depth: bool = False) -> dict:
+        return zd_info(self._h, depth)
+
+    def check(self):
+        zd_check(self._h)
 
     def knn(self, k: int, queries: torch.Tensor | None = None, stream=None):
         """All-points rows (queries None, one row per id) or external queries
@@ -313,6 +335,10 @@ def zd_forest_run(forest, stream=None):
     _check(lib().zd_forest_run(forest, _stream(stream)), "zd_forest_run")
 
 
+def zd_forest_check(forest):
+    _check(lib().zd_forest_check(forest), "zd_forest_check")
+
+
 def zd_forest_free(forest):
     if forest:
         _check(lib().zd_forest_free(forest), "zd_forest_free")
@@ -334,6 +360,9 @@ class ZdForest:
         d2 = torch.empty((self.n, k), dtype=torch.float64, device="cuda")
         zd_forest_knn(self._h, k, ids, d2, stream)
         return ids, d2
+
+    def check(self):
+        zd_forest_check(self._h)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -363,6 +392,9 @@ class ZdForestPlan:
     def run(self, stream=None):
         zd_forest_run(self._h, stream)
         return self.ids, self.d2
+
+    def check(self):
+        zd_forest_check(self._h)
 
     def close(self):
         if getattr(self, "_h", None):

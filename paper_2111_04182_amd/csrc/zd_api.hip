@@ -78,6 +78,7 @@ struct zd_tree_s {
   int64_t icap = 0;  // allocated length of the id arrays
   hipStream_t stream = nullptr;
   bool broken = false;
+  int64_t walk_limit = 0;  // test hook: steps a search may take (0: unbounded in practice)
   Store st;
   int32_t *slot_of = nullptr;  // [icap] id -> sorted position, -1 if dead
   int32_t *mark = nullptr;     // [icap] zero between calls
@@ -96,7 +97,9 @@ struct zd_tree_s {
     v.leaf_parent = st.leaf_parent;
     v.inode = st.inode;
     v.meta = meta;
+    v.walk_err = meta + kMetaWalkErr;
     v.n = st.n;
+    v.walk_limit = walk_limit;
     return v;
   }
 
@@ -131,6 +134,20 @@ hipError_t bind_stream(zd_tree t, hipStream_t s) {
   if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
   (void)hipEventDestroy(ev);
   if (e == hipSuccess) t->stream = s;
+  return e;
+}
+
+// Order a query on stream `s` after the tree's pending work on its own stream,
+// and the tree's later work (updates, release) after the query, without
+// changing the tree: concurrent queries on other streams only read it.
+hipError_t join_query_stream(zd_tree t, hipStream_t s, bool after) {
+  if (s == t->stream) return hipSuccess;
+  hipEvent_t ev;
+  hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e != hipSuccess) return e;
+  e = after ? hipEventRecord(ev, s) : hipEventRecord(ev, t->stream);
+  if (e == hipSuccess) e = after ? hipStreamWaitEvent(t->stream, ev, 0) : hipStreamWaitEvent(s, ev, 0);
+  (void)hipEventDestroy(ev);
   return e;
 }
 
@@ -196,17 +213,39 @@ void destroy(zd_tree t) {
   delete t;
 }
 
-// One int32 from device memory, read on stream s through the thread's
-// pinned buffer (a pageable destination costs a staged copy).
-hipError_t read_i32(const int32_t *dptr, int32_t *out, hipStream_t s) {
+// `count` int32 words from device memory (count <= 16), read on stream s
+// through the thread's pinned buffer (a pageable destination costs a staged
+// copy).
+hipError_t read_i32s(const int32_t *dptr, int32_t *out, int count, hipStream_t s) {
   int32_t *h = host_flag();
-  hipError_t e = hipMemcpyAsync(h ? h : out, dptr, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  hipError_t e =
+      hipMemcpyAsync(h ? h : out, dptr, sizeof(int32_t) * count, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e == hipSuccess && h) *out = *h;
+  if (e == hipSuccess && h)
+    for (int i = 0; i < count; ++i) out[i] = h[i];
   return e;
 }
 
-constexpr int64_t kMaxPoints = (int64_t)INT32_MAX - 1;
+hipError_t read_i32(const int32_t *dptr, int32_t *out, hipStream_t s) {
+  return read_i32s(dptr, out, 1, s);
+}
+
+// Read the tree's meta words (synchronises its stream).  A corrupted climb
+// in the build or a search that gave up marks the tree broken: ZD_EDEVICE.
+zd_status read_meta(zd_tree t, int32_t *meta) {
+  hipError_t e = read_i32s(t->meta, meta, kMetaCount, t->stream);
+  if (e != hipSuccess) {
+    t->broken = true;
+    return to_status(e);
+  }
+  if (meta[kMetaBuildErr] != 0 || meta[kMetaWalkErr] != 0) {
+    t->broken = true;
+    return ZD_EDEVICE;
+  }
+  return ZD_OK;
+}
+
+constexpr int64_t kMaxIds = (int64_t)INT32_MAX - 1;  // ids are int32, -1 pads
 
 }  // namespace
 
@@ -229,7 +268,7 @@ zd_status zd_build(const zd_params *p, const double *xyz, int64_t n, void *strea
                    zd_tree *out) {
   if (!p || !out) return ZD_EINVAL;
   const int dim = p->dim;
-  if ((dim != 2 && dim != 3) || p->leaf_size < 1 || n < 0 || n > kMaxPoints) return ZD_EINVAL;
+  if ((dim != 2 && dim != 3) || p->leaf_size < 1 || n < 0 || n > kMaxLive) return ZD_EINVAL;
   if (!valid_query_waves(p->query_waves)) return ZD_EINVAL;
   if (n > 0 && !xyz) return ZD_EINVAL;
   if ((p->box_lo == nullptr) != (p->box_hi == nullptr)) return ZD_EINVAL;
@@ -330,9 +369,9 @@ zd_status zd_knn(zd_tree t, const double *q_xyz, int64_t m, int32_t k, int32_t *
   if (t->broken) return ZD_EDEVICE;
   if (m > 0 && (!out_ids || !out_d2)) return ZD_EINVAL;
   if (!q_xyz && m != t->cap) return ZD_EINVAL;
-  if (q_xyz && m > kMaxPoints) return ZD_EINVAL;
+  if (q_xyz && m > kMaxLive) return ZD_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = bind_stream(t, s);
+  hipError_t e = join_query_stream(t, s, false);
   if (e == hipSuccess && m > 0) {
     if (!q_xyz) {
       if (t->cap > t->st.n) e = fill_dead_rows(t->slot_of, t->cap, k, out_ids, out_d2, s);
@@ -342,8 +381,10 @@ zd_status zd_knn(zd_tree t, const double *q_xyz, int64_t m, int32_t k, int32_t *
       e = knn_external(t->dim, t->view(), t->geo, q_xyz, m, k, out_ids, out_d2, s, t->qwaves);
     }
   }
+  if (e == hipSuccess) e = join_query_stream(t, s, true);
   if (e != hipSuccess) {
-    t->broken = e != hipErrorOutOfMemory;
+    // (a failed query leaves the tree as it was; only the caller's stream
+    // state is in doubt, so the tree is not marked broken here)
     return to_status(e);
   }
   return ZD_OK;
@@ -354,20 +395,23 @@ zd_status zd_insert_batch(zd_tree t, const double *xyz, int64_t m, int32_t *out_
   if (!t || m < 0) return ZD_EINVAL;
   if (t->broken) return ZD_EDEVICE;
   if (m == 0) return ZD_OK;
-  if (!xyz || t->cap + m > kMaxPoints) return ZD_EINVAL;
+  if (!xyz || t->cap + m > kMaxIds || t->st.n + m > kMaxLive) return ZD_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   const int dim = t->dim;
   hipError_t e = bind_stream(t, s);
-  // 1. validate the whole batch against the declared box
-  int32_t bad = 0;
-  if (e == hipSuccess) e = fill_i32(t->meta + kMetaErr, 0, 1, s);
-  if (e == hipSuccess) e = count_outside_box(dim, xyz, m, t->geo.lo, t->hi, t->meta + kMetaErr, s);
-  if (e == hipSuccess) e = read_i32(t->meta + kMetaErr, &bad, s);
+  // 1. validate the whole batch against the declared box (and read the
+  // tree's error counts with the same synchronisation)
+  int32_t meta[kMetaCount];
+  if (e == hipSuccess) e = fill_i32(t->meta + kMetaCheck, 0, 1, s);
+  if (e == hipSuccess)
+    e = count_outside_box(dim, xyz, m, t->geo.lo, t->hi, t->meta + kMetaCheck, s);
   if (e != hipSuccess) {
     t->broken = true;
     return to_status(e);
   }
-  if (bad) return ZD_EBOUNDS;
+  const zd_status ms = read_meta(t, meta);
+  if (ms != ZD_OK) return ms;
+  if (meta[kMetaCheck]) return ZD_EBOUNDS;
   // 2. key and sort the batch (Algorithm 4 starts from a shifted, sorted batch)
   const int64_t n = t->st.n, n2 = n + m;
   uint64_t *bk = nullptr, *bk2 = nullptr;
@@ -423,13 +467,20 @@ zd_status zd_delete_batch(zd_tree t, const int32_t *ids, int64_t m, void *stream
   hipStream_t s = (hipStream_t)stream;
   const int dim = t->dim;
   hipError_t e = bind_stream(t, s);
-  // 1. validate: every id in range, live, and unique in the batch
-  int32_t bad = 0;
-  if (e == hipSuccess) e = fill_i32(t->meta + kMetaErr, 0, 1, s);
+  // 1. validate: every id in range, live, and unique in the batch (the
+  // tree's error counts are read with the same synchronisation)
+  int32_t meta[kMetaCount];
+  if (e == hipSuccess) e = fill_i32(t->meta + kMetaCheck, 0, 1, s);
   if (e == hipSuccess)
-    e = validate_delete(ids, m, t->cap, t->slot_of, t->mark, t->meta + kMetaErr, s);
-  if (e == hipSuccess) e = read_i32(t->meta + kMetaErr, &bad, s);
-  if (e == hipSuccess && bad) e = unmark_ids(ids, m, t->cap, t->mark, s);
+    e = validate_delete(ids, m, t->cap, t->slot_of, t->mark, t->meta + kMetaCheck, s);
+  if (e != hipSuccess) {
+    t->broken = true;
+    return to_status(e);
+  }
+  const zd_status ms = read_meta(t, meta);
+  if (ms != ZD_OK) return ms;
+  const int32_t bad = meta[kMetaCheck];
+  if (bad) e = unmark_ids(ids, m, t->cap, t->mark, s);
   if (e != hipSuccess) {
     t->broken = true;
     return to_status(e);
@@ -475,17 +526,41 @@ zd_status zd_free(zd_tree t) {
 }
 
 zd_status zd_info(zd_tree t, int64_t *n_live, int64_t *id_capacity, int64_t *n_leaves,
-                  int64_t *n_internal) {
+                  int64_t *n_internal, int32_t *depth) {
   if (!t) return ZD_EINVAL;
-  int32_t I = 0;
-  if (t->st.n > 0) {
-    hipError_t e = read_i32(t->meta + kMetaInternal, &I, t->stream);
-    if (e != hipSuccess) return to_status(e);
+  if (t->broken) return ZD_EDEVICE;
+  int32_t meta[kMetaCount];
+  zd_status st = read_meta(t, meta);
+  if (st != ZD_OK) return st;
+  const int32_t I = t->st.n > 0 ? meta[kMetaInternal] : 0;
+  int32_t dep = 0;
+  if (depth && t->st.n > 0) {
+    hipError_t e = tree_depth(t->st.leaf_parent, t->st.inode, (int64_t)I + 1,
+                              t->meta + kMetaDepth, t->stream);
+    if (e == hipSuccess) e = read_i32(t->meta + kMetaDepth, &dep, t->stream);
+    if (e != hipSuccess) {
+      t->broken = true;
+      return to_status(e);
+    }
   }
   if (n_live) *n_live = t->st.n;
   if (id_capacity) *id_capacity = t->cap;
   if (n_leaves) *n_leaves = t->st.n > 0 ? (int64_t)I + 1 : 0;
-  if (n_internal) *n_internal = t->st.n > 0 ? I : 0;
+  if (n_internal) *n_internal = I;
+  if (depth) *depth = dep;
+  return ZD_OK;
+}
+
+zd_status zd_check(zd_tree t) {
+  if (!t) return ZD_EINVAL;
+  if (t->broken) return ZD_EDEVICE;
+  int32_t meta[kMetaCount];
+  return read_meta(t, meta);
+}
+
+zd_status zd_set_walk_limit(zd_tree t, int64_t steps) {
+  if (!t || steps < 0) return ZD_EINVAL;
+  t->walk_limit = steps;
   return ZD_OK;
 }
 
@@ -504,10 +579,13 @@ zd_status zd_export(zd_tree t, uint64_t *keys, int32_t *ids, int64_t *leaf_count
     for (int c = 0; c < dim; ++c) shift_out[c] = t->geo.shift[c];
   const int64_t n = t->st.n;
   if (n == 0) return ZD_OK;
+  if (t->broken) return ZD_EDEVICE;
   hipStream_t s = t->stream;
-  int32_t I = 0;
-  hipError_t e = read_i32(t->meta + kMetaInternal, &I, s);
-  if (e != hipSuccess) return to_status(e);
+  int32_t meta[kMetaCount];
+  const zd_status ms = read_meta(t, meta);
+  if (ms != ZD_OK) return ms;
+  const int32_t I = meta[kMetaInternal];
+  hipError_t e = hipSuccess;
   const int64_t nl = (int64_t)I + 1;
   std::vector<int32_t> lb(nl + 1), lp(nl);
   std::vector<INode> in((size_t)I);
@@ -615,7 +693,7 @@ zd_status forest_setup(const zd_params *p, const double *xyz, int64_t n, const i
                        int32_t C, const int32_t *leaf_sizes, hipStream_t s, zd_forest *out) {
   if (!p || !out || !offsets || C < 1) return ZD_EINVAL;
   const int dim = p->dim;
-  if ((dim != 2 && dim != 3) || p->leaf_size < 1 || n < 0 || n > kMaxPoints) return ZD_EINVAL;
+  if ((dim != 2 && dim != 3) || p->leaf_size < 1 || n < 0 || n > kMaxLive) return ZD_EINVAL;
   if (!valid_query_waves(p->query_waves)) return ZD_EINVAL;
   if (n > 0 && !xyz) return ZD_EINVAL;
   if ((p->box_lo == nullptr) != (p->box_hi == nullptr)) return ZD_EINVAL;
@@ -813,6 +891,11 @@ zd_status zd_forest_run(zd_forest f, void *stream) {
   hipError_t e = bind_stream(f->t, s);
   if (e == hipSuccess) e = hipGraphLaunch(f->exec, s);
   return to_status(e);
+}
+
+zd_status zd_forest_check(zd_forest f) {
+  if (!f) return ZD_EINVAL;
+  return zd_check(f->t);
 }
 
 zd_status zd_forest_free(zd_forest f) {

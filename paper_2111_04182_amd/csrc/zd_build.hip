@@ -389,7 +389,11 @@ __global__ void __launch_bounds__(kLeafBlock)
   };
   int32_t l = (int32_t)j, r = (int32_t)j;
   int32_t node = ~(int32_t)j;
-  for (int guard = 0; guard < 130; ++guard) {
+  // every climb ends at the root or hands its node to the sibling's climb
+  // within one step per level (at most 64 levels per cloud, plus the levels
+  // that separate a forest's clouds); running out of steps is a corruption
+  int guard = 0;
+  for (; guard < 130; ++guard) {
     if (l == 0 && r == I) {
       meta[kMetaRoot] = node;
       if (node < 0) leaf_parent[~node] = -1;
@@ -449,11 +453,35 @@ __global__ void __launch_bounds__(kLeafBlock)
     }
     // a corrupted exchange ends the climb instead of indexing out of range
     if (l < 0 || r > I || l > r) {
-      atomicAdd(&meta[kMetaErr], 1);
+      atomicAdd(&meta[kMetaBuildErr], 1);
       break;
     }
     node = p;
   }
+  if (guard == 130) atomicAdd(&meta[kMetaBuildErr], 1);
+}
+
+// One thread per leaf: count the links up to the root.
+__global__ void k_leaf_depth(const int32_t *__restrict__ leaf_parent,
+                             const INode *__restrict__ inode, int64_t nl, int32_t *depth) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nl) return;
+  int32_t d = 0;
+  int32_t link = leaf_parent[j];
+  while (link >= 0 && d < 1024) {
+    ++d;
+    link = inode[link >> 1].parent;
+  }
+  atomicMax(depth, d);
+}
+
+hipError_t tree_depth(const int32_t *leaf_parent, const INode *inode, int64_t n_leaves,
+                      int32_t *depth, hipStream_t s) {
+  hipError_t e = fill_i32(depth, 0, 1, s);
+  if (e != hipSuccess || n_leaves <= 0) return e;
+  k_leaf_depth<<<(unsigned)((n_leaves + 255) / 256), 256, 0, s>>>(leaf_parent, inode, n_leaves,
+                                                                  depth);
+  return hipGetLastError();
 }
 
 hipError_t build_tree_links(int dim, int leaf_size, int64_t n, const BuildBuffers &b,

@@ -69,11 +69,29 @@ struct TreeView {
   const int32_t *leaf_parent;  // [n_leaves] (parent << 1) | side, -1 if root
   const INode *inode;       // [n_internal]
   const int32_t *meta;      // meta[0] = n_internal, meta[1] = root
+  int32_t *walk_err;        // &meta[kMetaWalkErr]: counts searches that gave up
   int64_t n;
+  int64_t walk_limit;       // steps a search may take; 0: 4n + 256 (never reached)
 };
 
-// meta[] slots
-enum { kMetaInternal = 0, kMetaRoot = 1, kMetaErr = 2, kMetaCount = 4 };
+// meta[] slots: the internal node count and root of the tree; a status word
+// for the validation of updates; the count of corrupted climbs in the build
+// and of searches that gave up (both stay zero on a valid tree, and are read
+// at the next call that synchronises); the depth, when asked for.
+enum {
+  kMetaInternal = 0,
+  kMetaRoot = 1,
+  kMetaCheck = 2,
+  kMetaBuildErr = 3,
+  kMetaWalkErr = 4,
+  kMetaDepth = 5,
+  kMetaCount = 8
+};
+
+// Links are stored as (node << 1) | side in int32, so node indices, and
+// with them the points of one tree (internal nodes <= points - 1), stay
+// below 2^30.
+constexpr int64_t kMaxLive = (int64_t(1) << 30) - 1;
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -261,6 +279,9 @@ hipError_t gather_points(int dim, const double *xyz, int64_t stride, const int32
                          hipStream_t s, const double *aos = nullptr);
 hipError_t build_tree_links(int dim, int leaf_size, int64_t n, const BuildBuffers &b,
                             hipStream_t s);
+// the largest number of edges from the root to a leaf, into *depth (device)
+hipError_t tree_depth(const int32_t *leaf_parent, const INode *inode, int64_t n_leaves,
+                      int32_t *depth, hipStream_t s);
 
 // Queries.  groups == nullptr: wavefront w answers sorted positions
 // [64w, 64w + 64); otherwise wavefront w answers [groups[w].x, groups[w].y],

@@ -521,6 +521,7 @@ struct WaveSearch {
   int32_t skip_lo, skip_hi;      // sorted positions already scored (all lanes)
   int32_t own_lo, own_n;         // external queries: this lane's scored leaf
   int64_t budget;                // walk bound (never reached on a valid tree)
+  bool gave_up = false;          // the walk stopped before it finished
   uint64_t key_ref;              // Morton key of the group's middle query (child order)
   typename HeapFor<K>::type h;
   __device__ __forceinline__ WaveSearch(const TreeView &t_, Cand *stage_) : t(t_), stage(stage_) {}
@@ -692,7 +693,10 @@ struct WaveSearch {
         // point's cell (an order heuristic only; it never changes the rows)
         const int bit = uni(N->bit);
         const int first = bit < 64 ? (int)((key_ref >> bit) & 1) : 0;
-        if (sp >= 64) return;
+        if (sp >= 64) {
+          gave_up = true;
+          return;
+        }
         if ((int)(threadIdx.x & 63) == sp) stk = (n << 1) | (1 - first);
         ++sp;
         s = first;
@@ -739,6 +743,14 @@ struct WaveSearch {
       }
       link = uni(P->parent);
     }
+    if (budget <= 0) gave_up = true;
+  }
+
+  // A search that gave up (a corrupted tree, or the step limit a test sets)
+  // is counted where the next synchronising call of the library reads it:
+  // its rows are not exact, and the tree is reported broken.
+  __device__ __forceinline__ void report() const {
+    if (gave_up && (threadIdx.x & 63) == 0) atomicAdd(t.walk_err, 1);
   }
 };
 
@@ -835,7 +847,7 @@ k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
   s.pz = D == 3 ? t.Z[i] : 0.0;
   s.self = t.id[i];
   const int mid = (int)((last - g0) / 2);
-  s.budget = 4 * t.n + 256;
+  s.budget = t.walk_limit > 0 ? t.walk_limit : 4 * t.n + 256;
   s.key_ref = uni((int32_t)(t.key[g0 + mid] >> 32));
   s.key_ref = (s.key_ref << 32) | (uint32_t)uni((int32_t)t.key[g0 + mid]);
   s.h.init(k, s.valid);
@@ -860,6 +872,7 @@ k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
     G = x;
   }
   s.run_from(G);
+  s.report();
   if (s.valid) s.h.write(k, out_ids + (int64_t)s.self * k, out_d2 + (int64_t)s.self * k);
 }
 
@@ -897,7 +910,7 @@ k_knn_ext(TreeView t, const double *__restrict__ q,
   s.pz = D == 3 ? q[2 * m + r] : 0.0;
   s.self = -1;
   const int mid = (int)((last - g0) / 2);
-  s.budget = 4 * t.n + 256;
+  s.budget = t.walk_limit > 0 ? t.walk_limit : 4 * t.n + 256;
   s.skip_lo = 1;
   s.skip_hi = 0;
   s.key_ref = uni((int32_t)(qkey[g0 + mid] >> 32));
@@ -928,7 +941,9 @@ k_knn_ext(TreeView t, const double *__restrict__ q,
         const int bit = N->bit;
         x = N->child[(int)((myk >> bit) & 1)];
       }
-      // (x >= 0 here only on a corrupted tree: nothing is scored then)
+      // (x >= 0 here only on a corrupted tree: nothing is scored then, and
+      // the search is reported as given up)
+      if (__ballot(s.valid && x >= 0) != 0) s.gave_up = true;
       const int32_t lb = x < 0 ? t.leaf_begin[~x] : 0, le = x < 0 ? t.leaf_begin[~x + 1] : 0;
       s.own_lo = lb;
       s.own_n = s.valid ? le - lb : 0;
@@ -942,6 +957,7 @@ k_knn_ext(TreeView t, const double *__restrict__ q,
       }
     }
     s.run_from(node);
+    s.report();
   }
   if (s.valid) s.h.write(k, out_ids + (int64_t)r * k, out_d2 + (int64_t)r * k);
 }

@@ -63,6 +63,7 @@ def test_forest_rows_match_per_cloud_oracle(dim, k):
     P, off = mixed_clouds(10 + dim, dim)
     f = zd.ZdForest(dev(P), off, leaf_size=16, shift_seed=3)
     same(f.knn(k), oracle_rows(P, off, k), f"forest d={dim} k={k}")
+    f.check()
     f.close()
 
 
@@ -119,6 +120,7 @@ def test_forest_graph_replays():
     ids, d2 = plan.run()
     torch.cuda.synchronize()
     same((ids, d2), oracle_rows(P2, off, 12), "replay on new coordinates")
+    plan.check()
     plan.close()
 
 

@@ -30,8 +30,11 @@ def test_header_declares_the_boundary():
 
 
 def test_library_exports_every_declared_symbol(L):
+    import paper_2111_04182_amd._lib as B
     for n in declared_functions():
         assert hasattr(L, n), n
+    # the binding wraps exactly the declared calls
+    assert sorted(B.EXPORTED) == sorted(declared_functions())
 
 
 def test_status_strings(L):
@@ -45,7 +48,9 @@ def test_argument_errors_need_no_device(L):
     vp = C.c_void_p
     out = vp()
     assert L.zd_build(None, None, 0, None, C.byref(out)) == B.ZD_EINVAL
-    for dim, leaf, n in ((4, 16, 10), (1, 16, 10), (3, 0, 10), (3, 16, -1), (2, 16, 2**31)):
+    # n above 2^30 - 1: node links (node << 1) | side would overflow int32
+    for dim, leaf, n in ((4, 16, 10), (1, 16, 10), (3, 0, 10), (3, 16, -1), (2, 16, 2**31),
+                         (3, 16, 2**30), (2, 1, 2**30)):
         p = B._Params(dim, leaf, 0, None, None, None)
         assert L.zd_build(C.byref(p), vp(1), n, None, C.byref(out)) == B.ZD_EINVAL
     for w in (-1, 3, 5, 8):  # query_waves must be 0, 1, 2 or 4
@@ -57,7 +62,9 @@ def test_argument_errors_need_no_device(L):
     assert L.zd_knn(None, None, 0, 1, None, None, None) == B.ZD_EINVAL
     assert L.zd_insert_batch(None, None, 1, None, None) == B.ZD_EINVAL
     assert L.zd_delete_batch(None, None, 1, None) == B.ZD_EINVAL
-    assert L.zd_info(None, None, None, None, None) == B.ZD_EINVAL
+    assert L.zd_info(None, None, None, None, None, None) == B.ZD_EINVAL
+    assert L.zd_check(None) == B.ZD_EINVAL
+    assert L.zd_set_walk_limit(None, 0) == B.ZD_EINVAL
     assert L.zd_free(None) == B.ZD_OK
     assert L.zd_knn_backward(4, None, 0, 0, 1, None, None, None, None) == B.ZD_EINVAL
     assert L.zd_knn_backward(3, None, 10, 20, 1, None, None, None, None) == B.ZD_EINVAL
@@ -84,3 +91,14 @@ def test_params_layout_matches_the_header(tmp_path):
                                           text=True).stdout.split()]
     assert got[0] == C.sizeof(B._Params)
     assert got[1:] == [getattr(B._Params, f).offset for f in fields]
+
+
+def test_k_buckets_cover_kmax():
+    """The bucket list the GPU tests iterate over is the kernels' own, rising,
+    and its top bucket is ZD_KMAX."""
+    from tests.kbuckets import bucket_cases, k_buckets, k_max
+    b = k_buckets()
+    assert b == sorted(set(b)) and b[0] == 1 and b[-1] == k_max()
+    import paper_2111_04182_amd._lib as B
+    assert B.ZD_KMAX == k_max()
+    assert len(bucket_cases()) == 2 * len(b) - 1

@@ -414,3 +414,51 @@ def test_gradient_translation_invariance():
     g = np.random.default_rng(84).random(ids.shape)
     grad = oracle.knn_grad(P, ids, g)
     assert np.abs(grad.sum(axis=0)).max() < 1e-12
+
+
+def _parse_counter_trees(path):
+    trees, cur = [], None
+    with open(path) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            w = line.split()
+            if w[0] == "tree":
+                cur = dict(name=w[1], L=int(w[2]), pts=[], rows=[])
+            elif w[0] == "end":
+                trees.append(cur)
+                cur = None
+            elif w[0] in ("all", "root", "ext"):
+                cur["rows"].append((w[0], w[1], int(w[2]), int(w[3]), int(w[4])))
+            else:
+                cur["pts"].append([float(v) for v in w])
+    return trees
+
+
+def test_work_counters_hand_counted(golden_dir):
+    """Candidates scored and boxes tested per query, counted by hand from
+    Algorithms 2 and 3 on two tiny trees (tests/golden/tiny_counters.txt)."""
+    trees = _parse_counter_trees(os.path.join(golden_dir, "tiny_counters.txt"))
+    assert len(trees) == 2
+    n_rows = 0
+    for tr in trees:
+        P = np.array(tr["pts"])
+        t = oracle.Tree(P, tr["L"], box=(np.zeros(2), np.full(2, 8.0)),
+                        shift=np.zeros(2, dtype=np.uint64))
+        for mode, q, k, cand, box in tr["rows"]:
+            if mode == "ext":
+                Q = np.array([[float(v) for v in q.split(",")]])
+                _, _, c, b = t.knn(Q, k, work=True)
+            elif mode == "root":
+                _, _, c, b = t.knn_root(k, qids=[int(q)], work=True)
+            else:
+                _, _, c, b = t.knn_all(k, qids=[int(q)], work=True)
+            assert (int(c[0]), int(b[0])) == (cand, box), (tr["name"], mode, q, k)
+            n_rows += 1
+        # the per-call totals are the sums of the per-row counts
+        _, _, c, b = t.knn_all(1, work=True)
+        tot = t.counters()
+        assert (tot["candidates"], tot["box_tests"]) == (int(c.sum()), int(b.sum()))
+        t.close()
+    assert n_rows == 14
