@@ -59,7 +59,8 @@ typedef enum {
   ZD_EID = 3,     /* a deleted id is out of range, dead, or repeated */
   ZD_ENOMEM = 4,  /* device allocation failed */
   ZD_EDEVICE = 5, /* a HIP call failed; only zd_free remains valid */
-  ZD_EKMAX = 6    /* k exceeds ZD_KMAX */
+  ZD_EKMAX = 6,   /* k exceeds ZD_KMAX */
+  ZD_ELIMIT = 7   /* beyond the fixed scratch of zd_knn_noalloc */
 } zd_status;
 
 /* largest supported k */
@@ -137,6 +138,26 @@ ZD_API zd_status zd_build(const zd_params *params, const double *xyz, int64_t n,
  * ZD_EDEVICE (a broken tree, or a HIP failure). */
 ZD_API zd_status zd_knn(zd_tree tree, const double *q_xyz, int64_t m, int32_t k,
                  int32_t *out_ids, double *out_d2, void *stream);
+
+/* zd_knn without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, rows and errors as zd_knn; the call
+ * makes no allocation of any kind (no hipMalloc, no library cache, no event).
+ *   - External queries (q_xyz != NULL) take their scratch (query keys,
+ *     order and sort buffers, about 24 bytes per query) from one fixed
+ *     32 MiB device array per GPU, held until the process ends; at most
+ *     2^20 = 1,048,576 queries per call, otherwise ZD_ELIMIT before anything
+ *     is enqueued.  All-points rows (q_xyz == NULL) need no scratch and take
+ *     any size zd_knn takes.
+ *   - Every call on one GPU shares that GPU's array: calls that overlap in
+ *     time on one GPU (two host threads, or two streams not ordered by the
+ *     caller) race on it and may return wrong rows.  Order them.
+ *   - Nothing orders the call against the tree's own stream: issue it on
+ *     that stream, or order it after the tree's last build or update (and
+ *     the tree's next update after it) yourself.
+ * Errors: as zd_knn, plus ZD_ELIMIT. */
+ZD_API zd_status zd_knn_noalloc(zd_tree tree, const double *q_xyz, int64_t m, int32_t k,
+                                int32_t *out_ids, double *out_d2, void *stream);
 
 /* Batch insertion (Algorithm 4).  The m new points get ids id_capacity,
  * id_capacity + 1, ...; the id capacity grows by m.

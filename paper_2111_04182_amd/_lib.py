@@ -17,10 +17,10 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libzd.so")
 
-ZD_OK, ZD_EINVAL, ZD_EBOUNDS, ZD_EID, ZD_ENOMEM, ZD_EDEVICE, ZD_EKMAX = range(7)
+ZD_OK, ZD_EINVAL, ZD_EBOUNDS, ZD_EID, ZD_ENOMEM, ZD_EDEVICE, ZD_EKMAX, ZD_ELIMIT = range(8)
 ZD_KMAX = 64
 
-EXPORTED = ("zd_build", "zd_knn", "zd_insert_batch", "zd_delete_batch", "zd_free", "zd_info",
+EXPORTED = ("zd_build", "zd_knn", "zd_knn_noalloc", "zd_insert_batch", "zd_delete_batch", "zd_free", "zd_info",
             "zd_check", "zd_set_walk_limit", "zd_export", "zd_knn_backward", "zd_forest_build", "zd_forest_knn", "zd_forest_plan",
             "zd_forest_run", "zd_forest_check", "zd_forest_free", "zd_status_str")
 
@@ -56,6 +56,8 @@ def lib() -> C.CDLL:
         L.zd_build.argtypes = [C.POINTER(_Params), vp, i64, vp, C.POINTER(vp)]
         L.zd_knn.restype = C.c_int
         L.zd_knn.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+        L.zd_knn_noalloc.restype = C.c_int
+        L.zd_knn_noalloc.argtypes = [vp, vp, i64, i32, vp, vp, vp]
         L.zd_insert_batch.restype = C.c_int
         L.zd_insert_batch.argtypes = [vp, vp, i64, vp, vp]
         L.zd_delete_batch.restype = C.c_int

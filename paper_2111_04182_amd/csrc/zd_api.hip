@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 using namespace zd;
@@ -260,6 +261,7 @@ const char *zd_status_str(zd_status status) {
     case ZD_ENOMEM: return "device allocation failed";
     case ZD_EDEVICE: return "device error";
     case ZD_EKMAX: return "k exceeds ZD_KMAX";
+    case ZD_ELIMIT: return "size beyond the fixed scratch of the allocation-free call";
   }
   return "unknown status";
 }
@@ -636,6 +638,95 @@ zd_status zd_knn_backward(int32_t dim, const double *xyz, int64_t stride, int64_
   if (rows > 0 && (!ids || !grad_d2)) return ZD_EINVAL;
   return to_status(
       knn_backward(dim, xyz, stride, rows, k, ids, grad_d2, grad_xyz, (hipStream_t)stream));
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// k-NN queries without any allocation: scratch in a fixed device array
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// The external-query path's scratch (query keys and order, their sort
+// buffers, digit counts and scan partials) for up to kNoAllocMaxQueries
+// queries, one copy per GPU for the life of the process.  In host code the
+// name `scratch` is only a stand-in: its device address, per device, comes
+// from hipGetSymbolAddress and is the only form passed to kernels.
+constexpr int64_t kNoAllocMaxQueries = int64_t(1) << 20;
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kScratchDevs = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevs] = {};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// An upper bound of what knn_external takes from the arena for m queries:
+// four arrays of m keys / ids, the sort's 256 digit counts per 4,096-key
+// tile, and per pass (at most 8) the scan's partial sums at up to two levels.
+size_t noalloc_need(int64_t m) {
+  const size_t tiles = (size_t)((m + kSortTileKeys - 1) / kSortTileKeys);
+  const size_t counts = 256 * tiles;
+  const size_t sums = (counts + 4095) / 4096;
+  return 2 * align256(8 * (size_t)m) + 2 * align256(4 * (size_t)m) + align256(4 * counts) +
+         8 * 2 * align256(4 * sums + 4);
+}
+static_assert((size_t)(int64_t(1) << 20) * 24 + (size_t(2) << 20) <= kNoAllocScratchBytes,
+              "the largest allowed query batch fits the scratch");
+
+// This device's copy of `scratch` (looked up once per device, with that
+// device current).
+hipError_t scratch_on_device(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kScratchDevs) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+zd_status zd_knn_noalloc(zd_tree t, const double *q_xyz, int64_t m, int32_t k, int32_t *out_ids,
+                         double *out_d2, void *stream) {
+  if (!t || m < 0 || k < 1) return ZD_EINVAL;
+  if (k > ZD_KMAX) return ZD_EKMAX;
+  if (t->broken) return ZD_EDEVICE;
+  if (m > 0 && (!out_ids || !out_d2)) return ZD_EINVAL;
+  if (!q_xyz && m != t->cap) return ZD_EINVAL;
+  if (q_xyz && m > kNoAllocMaxQueries) return ZD_ELIMIT;
+  if (q_xyz && noalloc_need(m) > kNoAllocScratchBytes) return ZD_ELIMIT;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  if (m > 0) {
+    if (!q_xyz) {
+      // all-points rows use no scratch
+      if (t->cap > t->st.n) e = fill_dead_rows(t->slot_of, t->cap, k, out_ids, out_d2, s);
+      if (e == hipSuccess)
+        e = knn_all_points(t->dim, t->view(), k, out_ids, out_d2, s, t->qwaves);
+    } else {
+      void *base = nullptr;
+      e = scratch_on_device(&base);
+      if (e == hipSuccess) {
+        Arena a{static_cast<char *>(base), kNoAllocScratchBytes, 0};
+        arena_activate(&a);
+        e = knn_external(t->dim, t->view(), t->geo, q_xyz, m, k, out_ids, out_d2, s, t->qwaves);
+        arena_activate(nullptr);
+      }
+    }
+  }
+  return to_status(e);
 }
 
 }  // extern "C"

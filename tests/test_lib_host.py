@@ -38,8 +38,8 @@ def test_library_exports_every_declared_symbol(L):
 
 
 def test_status_strings(L):
-    for code in range(7):
-        assert L.zd_status_str(code)
+    for code in range(8):
+        assert L.zd_status_str(code) and L.zd_status_str(code) != b"unknown status"
     assert L.zd_status_str(99) == b"unknown status"
 
 
