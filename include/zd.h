@@ -139,6 +139,16 @@ ZD_API zd_status zd_build(const zd_params *params, const double *xyz, int64_t n,
 ZD_API zd_status zd_knn(zd_tree tree, const double *q_xyz, int64_t m, int32_t k,
                  int32_t *out_ids, double *out_d2, void *stream);
 
+/* Root-based exact k-NN (Section 2): Algorithm 2 from the root with an
+ * empty candidate set, no climb.  Same arguments, rows, ordering and errors
+ * as zd_knn (q_xyz == NULL: all-points rows by id, self excluded; else
+ * external queries); only the start of the search differs from zd_knn's
+ * leaf-based (all-points) and bit-based (external) searches, which the paper
+ * finds more robust on skewed data.  Asynchronous; concurrent with other
+ * queries like zd_knn. */
+ZD_API zd_status zd_knn_root(zd_tree tree, const double *q_xyz, int64_t m, int32_t k,
+                             int32_t *out_ids, double *out_d2, void *stream);
+
 /* zd_knn without any allocation, for callers that cannot allocate device
  * memory: code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc.  Same arguments, rows and errors as zd_knn; the call

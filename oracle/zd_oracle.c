@@ -278,7 +278,6 @@ typedef struct {
   int64_t n_live;
   node *root;
   /* work counters of the last query call */
-  int64_t cnt_cand, cnt_box, cnt_rows;
 } ztree;
 
 static node *node_new(void) {
@@ -361,6 +360,15 @@ static node *build_tree(const ztree *T, const entry *P, int64_t n, int b) {
 
 static int key_bits(int dim) { return dim * bits_per_dim(dim); } /* 64 or 63 */
 
+/* Work counters of the last query call made by this thread (candidates
+ * scored, boxes tested, rows answered).  Thread-local: independent queries
+ * on one tree may run on several threads (the search itself only reads the
+ * tree). */
+typedef struct {
+  int64_t cand, box, rows;
+} work_count;
+static _Thread_local work_count wk;
+
 /* ------------------------------------------------------------------------- */
 /* searchDown / searchUp                                                     */
 /* ------------------------------------------------------------------------- */
@@ -393,7 +401,7 @@ static void scan_leaf(ztree *T, const node *C, const double *p, int64_t self, ns
     double x[3] = {0, 0, 0};
     for (int c = 0; c < T->dim; ++c) x[c] = T->x[c][q];
     double d = sq_dist(T->dim, p, x);
-    T->cnt_cand++;
+    wk.cand++;
     if (N->size < N->k || cand_less(d, q, N->d2[N->k - 1], N->id[N->k - 1]))
       nset_insert(N, d, q);
   }
@@ -401,7 +409,7 @@ static void scan_leaf(ztree *T, const node *C, const double *p, int64_t self, ns
 
 /* searchDown(T, p, N) -- Algorithm 2 */
 static void search_down(ztree *T, const node *t, const double *p, int64_t self, nset *N) {
-  T->cnt_box++;
+  wk.box++;
   if (box_dist2(T->dim, p, t->lo, t->hi) > nset_radius(N)) return;
   if (t->leaf) { scan_leaf(T, t, p, self, N); return; }
   double dl = centre_dist2(T->dim, p, t->left->lo, t->left->hi);
@@ -582,8 +590,8 @@ static uint64_t key_of_id(const ztree *T, int64_t id) {
  * (test and measurement instrumentation; the search itself is unchanged). */
 static void note_work(const ztree *T, int64_t r, int64_t c0, int64_t b0, int64_t *row_cand,
                       int64_t *row_box) {
-  if (row_cand) row_cand[r] = T->cnt_cand - c0;
-  if (row_box) row_box[r] = T->cnt_box - b0;
+  if (row_cand) row_cand[r] = wk.cand - c0;
+  if (row_box) row_box[r] = wk.box - b0;
 }
 
 /* Leaf-based all-points rows (Section 2, "Upward search algorithm"): for
@@ -599,17 +607,17 @@ ZO_API int zo_knn_rows_work(void *h, const int64_t *qids, int64_t m, int k,
   N.d2 = (double *)malloc(sizeof(double) * (size_t)k);
   N.id = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
   if (!N.d2 || !N.id) { free(N.d2); free(N.id); return ZO_ENOMEM; }
-  T->cnt_cand = T->cnt_box = T->cnt_rows = 0;
+  wk.cand = wk.box = wk.rows = 0;
   for (int64_t r = 0; r < m; ++r) {
     int64_t id = qids ? qids[r] : r;
-    const int64_t c0 = T->cnt_cand, b0 = T->cnt_box;
+    const int64_t c0 = wk.cand, b0 = wk.box;
     N.size = 0;
     if (id >= 0 && id < T->cap && T->live[id] && T->root) {
       double p[3] = {0, 0, 0};
       for (int c = 0; c < T->dim; ++c) p[c] = T->x[c][id];
       const node *C = leaf_of_key(T->root, key_of_id(T, id));
       search_up(T, C, p, id, &N);
-      T->cnt_rows++;
+      wk.rows++;
     }
     note_work(T, r, c0, b0, row_cand, row_box);
     nset_emit(&N, out_ids + r * k, out_d2 + r * k);
@@ -637,17 +645,17 @@ ZO_API int zo_knn_ext_work(void *h, const double *q, int64_t m, int k,
   N.d2 = (double *)malloc(sizeof(double) * (size_t)k);
   N.id = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
   if (!N.d2 || !N.id) { free(N.d2); free(N.id); return ZO_ENOMEM; }
-  T->cnt_cand = T->cnt_box = T->cnt_rows = 0;
+  wk.cand = wk.box = wk.rows = 0;
   for (int64_t r = 0; r < m; ++r) {
     double p[3] = {0, 0, 0};
     for (int c = 0; c < T->dim; ++c) p[c] = q[c * m + r];
-    const int64_t c0 = T->cnt_cand, b0 = T->cnt_box;
+    const int64_t c0 = wk.cand, b0 = wk.box;
     N.size = 0;
     if (T->root) {
       const node *C = leaf_of_key(T->root, point_key(T->dim, p, T->lo, T->S, T->shift));
       search_up(T, C, p, -1, &N);
     }
-    T->cnt_rows++;
+    wk.rows++;
     note_work(T, r, c0, b0, row_cand, row_box);
     nset_emit(&N, out_ids + r * k, out_d2 + r * k);
   }
@@ -672,16 +680,16 @@ ZO_API int zo_knn_root_work(void *h, const int64_t *qids, int64_t m, int k,
   N.d2 = (double *)malloc(sizeof(double) * (size_t)k);
   N.id = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
   if (!N.d2 || !N.id) { free(N.d2); free(N.id); return ZO_ENOMEM; }
-  T->cnt_cand = T->cnt_box = T->cnt_rows = 0;
+  wk.cand = wk.box = wk.rows = 0;
   for (int64_t r = 0; r < m; ++r) {
     int64_t id = qids ? qids[r] : r;
-    const int64_t c0 = T->cnt_cand, b0 = T->cnt_box;
+    const int64_t c0 = wk.cand, b0 = wk.box;
     N.size = 0;
     if (id >= 0 && id < T->cap && T->live[id] && T->root) {
       double p[3] = {0, 0, 0};
       for (int c = 0; c < T->dim; ++c) p[c] = T->x[c][id];
       search_down(T, T->root, p, id, &N);
-      T->cnt_rows++;
+      wk.rows++;
     }
     note_work(T, r, c0, b0, row_cand, row_box);
     nset_emit(&N, out_ids + r * k, out_d2 + r * k);
@@ -698,10 +706,10 @@ ZO_API int zo_knn_root(void *h, const int64_t *qids, int64_t m, int k,
 
 /* candidates evaluated, box tests and rows of the last query call */
 ZO_API void zo_counters(void *h, int64_t *cand, int64_t *box, int64_t *rows) {
-  ztree *T = (ztree *)h;
-  *cand = T->cnt_cand;
-  *box = T->cnt_box;
-  *rows = T->cnt_rows;
+  (void)h;
+  *cand = wk.cand;
+  *box = wk.box;
+  *rows = wk.rows;
 }
 
 /* ------------------------------------------------------------------------- */

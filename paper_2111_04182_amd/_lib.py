@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libzd.so")
 ZD_OK, ZD_EINVAL, ZD_EBOUNDS, ZD_EID, ZD_ENOMEM, ZD_EDEVICE, ZD_EKMAX, ZD_ELIMIT = range(8)
 ZD_KMAX = 64
 
-EXPORTED = ("zd_build", "zd_knn", "zd_knn_noalloc", "zd_insert_batch", "zd_delete_batch", "zd_free", "zd_info",
+EXPORTED = ("zd_build", "zd_knn", "zd_knn_root", "zd_knn_noalloc", "zd_insert_batch", "zd_delete_batch", "zd_free", "zd_info",
             "zd_check", "zd_set_walk_limit", "zd_export", "zd_knn_backward", "zd_forest_build", "zd_forest_knn", "zd_forest_plan",
             "zd_forest_run", "zd_forest_check", "zd_forest_free", "zd_status_str")
 
@@ -56,6 +56,8 @@ def lib() -> C.CDLL:
         L.zd_build.argtypes = [C.POINTER(_Params), vp, i64, vp, C.POINTER(vp)]
         L.zd_knn.restype = C.c_int
         L.zd_knn.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+        L.zd_knn_root.restype = C.c_int
+        L.zd_knn_root.argtypes = [vp, vp, i64, i32, vp, vp, vp]
         L.zd_knn_noalloc.restype = C.c_int
         L.zd_knn_noalloc.argtypes = [vp, vp, i64, i32, vp, vp, vp]
         L.zd_insert_batch.restype = C.c_int
@@ -149,15 +151,26 @@ def zd_build(xyz: torch.Tensor, leaf_size: int = 16, box=None, shift_seed: int =
     return out
 
 
-def zd_knn(tree, q_xyz: torch.Tensor | None, m: int, k: int, out_ids: torch.Tensor,
-           out_d2: torch.Tensor, stream=None):
+def _knn_args(q_xyz, m, k, out_ids, out_d2):
     if q_xyz is not None:
         _check_soa(q_xyz)
     for t, dt in ((out_ids, torch.int32), (out_d2, torch.float64)):
         if not (t.is_cuda and t.dtype == dt and t.is_contiguous() and t.numel() >= m * k):
             raise ValueError("outputs must be contiguous CUDA tensors of m*k entries")
+
+
+def zd_knn(tree, q_xyz: torch.Tensor | None, m: int, k: int, out_ids: torch.Tensor,
+           out_d2: torch.Tensor, stream=None):
+    _knn_args(q_xyz, m, k, out_ids, out_d2)
     _check(lib().zd_knn(tree, _dptr(q_xyz), m, k, _dptr(out_ids), _dptr(out_d2),
                         _stream(stream)), "zd_knn")
+
+
+def zd_knn_root(tree, q_xyz: torch.Tensor | None, m: int, k: int, out_ids: torch.Tensor,
+                out_d2: torch.Tensor, stream=None):
+    _knn_args(q_xyz, m, k, out_ids, out_d2)
+    _check(lib().zd_knn_root(tree, _dptr(q_xyz), m, k, _dptr(out_ids), _dptr(out_d2),
+                             _stream(stream)), "zd_knn_root")
 
 
 def zd_insert_batch(tree, xyz: torch.Tensor, out_new_ids: torch.Tensor | None = None,
@@ -254,13 +267,14 @@ class ZdTree:
     def check(self):
         zd_check(self._h)
 
-    def knn(self, k: int, queries: torch.Tensor | None = None, stream=None):
+    def knn(self, k: int, queries: torch.Tensor | None = None, stream=None, root=False):
         """All-points rows (queries None, one row per id) or external queries
-        (SoA (d, m)).  Returns (ids int32 [rows, k], d2 float64 [rows, k])."""
+        (SoA (d, m)); root=True runs the root-based search instead.  Returns
+        (ids int32 [rows, k], d2 float64 [rows, k])."""
         m = self.cap if queries is None else queries.shape[1]
         ids = torch.empty((m, k), dtype=torch.int32, device="cuda")
         d2 = torch.empty((m, k), dtype=torch.float64, device="cuda")
-        zd_knn(self._h, queries, m, k, ids, d2, stream)
+        (zd_knn_root if root else zd_knn)(self._h, queries, m, k, ids, d2, stream)
         return ids, d2
 
     def insert(self, xyz: torch.Tensor, stream=None) -> torch.Tensor:

@@ -392,6 +392,26 @@ zd_status zd_knn(zd_tree t, const double *q_xyz, int64_t m, int32_t k, int32_t *
   return ZD_OK;
 }
 
+zd_status zd_knn_root(zd_tree t, const double *q_xyz, int64_t m, int32_t k, int32_t *out_ids,
+                      double *out_d2, void *stream) {
+  if (!t || m < 0 || k < 1) return ZD_EINVAL;
+  if (k > ZD_KMAX) return ZD_EKMAX;
+  if (t->broken) return ZD_EDEVICE;
+  if (m > 0 && (!out_ids || !out_d2)) return ZD_EINVAL;
+  if (!q_xyz && m != t->cap) return ZD_EINVAL;
+  if (q_xyz && m > kMaxLive) return ZD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = join_query_stream(t, s, false);
+  if (e == hipSuccess && m > 0) {
+    if (!q_xyz && t->cap > t->st.n)
+      e = fill_dead_rows(t->slot_of, t->cap, k, out_ids, out_d2, s);
+    if (e == hipSuccess)
+      e = knn_root_based(t->dim, t->view(), t->geo, q_xyz, m, k, out_ids, out_d2, s, t->qwaves);
+  }
+  if (e == hipSuccess) e = join_query_stream(t, s, true);
+  return to_status(e);
+}
+
 zd_status zd_insert_batch(zd_tree t, const double *xyz, int64_t m, int32_t *out_new_ids,
                           void *stream) {
   if (!t || m < 0) return ZD_EINVAL;

@@ -293,6 +293,11 @@ hipError_t knn_all_points(int dim, const TreeView &t, int k, int32_t *out_ids, d
 hipError_t knn_external(int dim, const TreeView &t, const Geometry &g, const double *q,
                         int64_t m, int k, int32_t *out_ids, double *out_d2, hipStream_t s,
                         int query_waves);
+// Root-based search (Section 2: Algorithm 2 from the root, empty candidate
+// set): all-points rows when q == nullptr (m ignored), else external queries.
+hipError_t knn_root_based(int dim, const TreeView &t, const Geometry &g, const double *q,
+                          int64_t m, int k, int32_t *out_ids, double *out_d2, hipStream_t s,
+                          int query_waves);
 hipError_t fill_dead_rows(const int32_t *slot_of, int64_t cap, int k, int32_t *out_ids,
                           double *out_d2, hipStream_t s);
 

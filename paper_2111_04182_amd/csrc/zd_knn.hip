@@ -1,6 +1,6 @@
 // zd_knn.hip -- host side of the k-NN queries: kernel choice per dimension
-// and k, the Morton presort of external queries (Section 3.1), and the
-// padding of rows that belong to deleted ids.  The search kernels themselves
+// and k, the Morton presort of external queries (Section 3.1), the
+// root-based variant, and the padding of rows that belong to deleted ids.  The search kernels themselves
 // are in zd_knn_impl.h.
 #include "zd_internal.h"
 
@@ -17,6 +17,13 @@ hipError_t knn_ext_d3(const TreeView &t, const double *q, const uint64_t *qkey,
                       const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
                       hipStream_t s, int query_waves);
 
+hipError_t knn_root_d2(const TreeView &t, const double *q, const uint64_t *qkey,
+                       const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
+                       hipStream_t s, int query_waves);
+hipError_t knn_root_d3(const TreeView &t, const double *q, const uint64_t *qkey,
+                       const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
+                       hipStream_t s, int query_waves);
+
 hipError_t knn_all_points(int dim, const TreeView &t, int k, int32_t *out_ids, double *out_d2,
                           hipStream_t s, int query_waves, const int4 *groups, int64_t ngroups) {
   if (t.n <= 0 || (groups && ngroups <= 0)) return hipSuccess;
@@ -24,12 +31,13 @@ hipError_t knn_all_points(int dim, const TreeView &t, int k, int32_t *out_ids, d
                   : knn_all_d2(t, k, out_ids, out_d2, s, groups, ngroups, query_waves);
 }
 
-hipError_t knn_external(int dim, const TreeView &t, const Geometry &g, const double *q,
-                        int64_t m, int k, int32_t *out_ids, double *out_d2, hipStream_t s,
-                        int query_waves) {
-  if (m <= 0) return hipSuccess;
-  // sort the queries by their Morton keys so a wavefront's 64 queries are
-  // neighbours in space; rows are still written in query order
+// External queries are sorted by their Morton keys so that a wavefront's 64
+// queries are neighbours in space (Section 3.1); rows are still written in
+// query order.  `root` selects the root-based start instead of the
+// bit-based descent.
+static hipError_t knn_presorted(int dim, const TreeView &t, const Geometry &g, const double *q,
+                                int64_t m, int k, int32_t *out_ids, double *out_d2,
+                                hipStream_t s, int query_waves, bool root) {
   uint64_t *key = nullptr, *key_tmp = nullptr;
   int32_t *order = nullptr, *order_tmp = nullptr;
   hipError_t e = dev_alloc_n(&key, m, s);
@@ -38,14 +46,40 @@ hipError_t knn_external(int dim, const TreeView &t, const Geometry &g, const dou
   if (e == hipSuccess) e = dev_alloc_n(&order_tmp, m, s);
   if (e == hipSuccess) e = encode_keys(g, q, m, m, 0, key, order, s);
   if (e == hipSuccess) e = radix_sort_pairs(key, order, key_tmp, order_tmp, m, dim * g.B, s);
-  if (e == hipSuccess)
-    e = dim == 3 ? knn_ext_d3(t, q, key, order, m, k, out_ids, out_d2, s, query_waves)
-                 : knn_ext_d2(t, q, key, order, m, k, out_ids, out_d2, s, query_waves);
+  if (e == hipSuccess) {
+    if (root)
+      e = dim == 3 ? knn_root_d3(t, q, key, order, m, k, out_ids, out_d2, s, query_waves)
+                   : knn_root_d2(t, q, key, order, m, k, out_ids, out_d2, s, query_waves);
+    else
+      e = dim == 3 ? knn_ext_d3(t, q, key, order, m, k, out_ids, out_d2, s, query_waves)
+                   : knn_ext_d2(t, q, key, order, m, k, out_ids, out_d2, s, query_waves);
+  }
   dev_release(key, s);
   dev_release(order, s);
   dev_release(key_tmp, s);
   dev_release(order_tmp, s);
   return e;
+}
+
+hipError_t knn_external(int dim, const TreeView &t, const Geometry &g, const double *q,
+                        int64_t m, int k, int32_t *out_ids, double *out_d2, hipStream_t s,
+                        int query_waves) {
+  if (m <= 0) return hipSuccess;
+  return knn_presorted(dim, t, g, q, m, k, out_ids, out_d2, s, query_waves, false);
+}
+
+hipError_t knn_root_based(int dim, const TreeView &t, const Geometry &g, const double *q,
+                          int64_t m, int k, int32_t *out_ids, double *out_d2, hipStream_t s,
+                          int query_waves) {
+  if (q) {
+    if (m <= 0) return hipSuccess;
+    return knn_presorted(dim, t, g, q, m, k, out_ids, out_d2, s, query_waves, true);
+  }
+  if (t.n <= 0) return hipSuccess;
+  return dim == 3 ? knn_root_d3(t, nullptr, nullptr, nullptr, t.n, k, out_ids, out_d2, s,
+                                query_waves)
+                  : knn_root_d2(t, nullptr, nullptr, nullptr, t.n, k, out_ids, out_d2, s,
+                                query_waves);
 }
 
 __global__ void k_dead_rows(const int32_t *__restrict__ slot_of, int64_t cap, int k,

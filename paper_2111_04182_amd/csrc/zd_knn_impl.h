@@ -962,6 +962,78 @@ k_knn_ext(TreeView t, const double *__restrict__ q,
   if (s.valid) s.h.write(k, out_ids + (int64_t)r * k, out_d2 + (int64_t)r * k);
 }
 
+// Root-based rows (Section 2): Algorithm 2 from the root with an empty
+// candidate set and no climb, the variant the paper contrasts with the
+// leaf- and bit-based starts.  q == nullptr: all-points rows, wavefront w
+// answering sorted positions [64w, 64w + 64) with each lane's own point
+// excluded (a one-point "own" range of the external-query scan); otherwise
+// Morton-presorted external queries as in k_knn_ext.  The shared walk is the
+// same as everywhere else; only its start differs.
+template <int D, int K>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(knn_ext_min_waves<K>())))
+k_knn_root(TreeView t, const double *__restrict__ q, const uint64_t *__restrict__ qkey,
+           const int32_t *__restrict__ order, int64_t m, int k, int32_t *__restrict__ out_ids,
+           double *__restrict__ out_d2) {
+  extern __shared__ __align__(16) char smem[];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int64_t g0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + w) * 64;
+  if (g0 >= m) return;
+  const int64_t last = min(g0 + 63, m - 1);
+  const int64_t i = min(g0 + lane, last);
+  const int mid = (int)((last - g0) / 2);
+  WaveSearch<D, K, true> s(t, nullptr);
+  bind_lds(s, smem, w);
+  s.valid = g0 + lane <= last;
+  int64_t row;
+  uint64_t kref;
+  if (q) {
+    const int32_t r = order[i];
+    s.px = q[r];
+    s.py = q[m + r];
+    s.pz = D == 3 ? q[2 * m + r] : 0.0;
+    s.own_lo = 0;
+    s.own_n = 0;
+    row = r;
+    kref = qkey[g0 + mid];
+  } else {
+    s.px = t.X[i];
+    s.py = t.Y[i];
+    s.pz = D == 3 ? t.Z[i] : 0.0;
+    s.own_lo = (int32_t)i;
+    s.own_n = s.valid ? 1 : 0;
+    row = t.id[i];
+    kref = t.key[g0 + mid];
+  }
+  s.self = -1;
+  s.budget = t.walk_limit > 0 ? t.walk_limit : 4 * t.n + 256;
+  s.skip_lo = 1;
+  s.skip_hi = 0;
+  s.key_ref = uni((int32_t)(kref >> 32));
+  s.key_ref = (s.key_ref << 32) | (uint32_t)uni((int32_t)kref);
+  s.h.init(k, s.valid);
+  const int32_t root = uni(t.meta[kMetaRoot]);
+  if (root != kNoRoot) {
+    // (the root's own box needs no test: the candidate set is empty)
+    if (root < 0) s.scan_leaf(~root);
+    else s.search_down(root);
+    if (s.budget <= 0) s.gave_up = true;
+    s.report();
+  }
+  if (s.valid) s.h.write(k, out_ids + row * k, out_d2 + row * k);
+}
+
+template <int D, int K>
+hipError_t launch_knn_root(const TreeView &t, const double *q, const uint64_t *qkey,
+                           const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
+                           hipStream_t s, int query_waves) {
+  const int64_t waves = (m + 63) / 64;
+  const int wpb = fit_waves<K>(query_waves);
+  k_knn_root<D, K><<<(unsigned)((waves + wpb - 1) / wpb), 64 * wpb, wpb * wave_lds_bytes<K>(), s>>>(
+      t, q, qkey, order, m, k, ids, d2);
+  return hipGetLastError();
+}
+
 template <int D, int K>
 hipError_t launch_knn_all(const TreeView &t, int k, int32_t *ids, double *d2, hipStream_t s,
                           const int4 *groups, int64_t ngroups, int query_waves) {

@@ -1,0 +1,18 @@
+// zd_knn_root_d2.hip -- root-based search kernels for 2-D trees, one per k bucket.
+#include "zd_knn_impl.h"
+
+namespace zd {
+
+hipError_t knn_root_d2(const TreeView &t, const double *q, const uint64_t *qkey,
+                       const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
+                       hipStream_t s, int query_waves) {
+  switch (k_bucket(k)) {
+#define X(KK) \
+  case KK: return launch_knn_root<2, KK>(t, q, qkey, order, m, k, ids, d2, s, query_waves);
+    ZD_FOR_EACH_K(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace zd

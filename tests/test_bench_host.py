@@ -33,3 +33,21 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in r.stderr
+
+
+def test_build_bytes_follow_the_compulsory_traffic():
+    # 3D: 112 B per point (24 read, 8 key, 20 sort pass, 48 gather, 8 keys,
+    # 4 id map) + 64 B per node; 2D: 88 B per point + 48 B per node
+    assert bench.build_bytes(10, 3) == 10 * 112 + 3 * 64
+    assert bench.build_bytes(10, 3, dim=2) == 10 * 88 + 3 * 48
+    assert 24 + 8 + 20 + 48 + 8 + 4 == 112
+
+
+def test_cpu_baseline_threads_match_serial():
+    import numpy as np
+    import workloads as W
+    P = W.uniform(20000, 3, 0)
+    _, qids, (ids, d2), cb = bench.cpu_baseline(P, 2000, 16)
+    assert cb["threaded_rows_equal_serial"]
+    assert cb["cores"] >= 1 and cb["nproc"] >= 1 and cb["cpu_model"]
+    assert len(qids) == 2000 and ids.shape == (2000, 10)

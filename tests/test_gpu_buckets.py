@@ -1,7 +1,8 @@
 """Every query kernel instantiation against the oracle's brute force.
 
-The search kernels are instantiated once per (dimension, k bucket,
-all-points | external queries); each runs here at the bucket's top k and at
+The search kernels are instantiated once per (dimension, k bucket, search:
+leaf-based all-points, bit-based external, root-based all-points and
+external); each runs here at the bucket's top k and at
 top - 1 (one padding slot), on an exact grid (every distance exactly
 representable, so ties in d2 are everywhere and the (d2, id) order decides)
 and on tight clusters with a sparse background.  Rows must equal brute force
@@ -56,7 +57,7 @@ def assert_rows(got, want, what):
     assert np.array_equal(gd, want[1]), f"{what}: d2 differ"
 
 
-@pytest.mark.parametrize("mode", ["all", "ext"])
+@pytest.mark.parametrize("mode", ["all", "ext", "root_all", "root_ext"])
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("data", ["grid", "clustered"])
 @pytest.mark.parametrize("k,bucket", bucket_cases(), ids=[f"k{k}-b{b}" for k, b in bucket_cases()])
@@ -64,9 +65,11 @@ def test_every_bucket_matches_brute_force(k, bucket, data, dim, mode):
     P, Q = case(data, dim)
     print(f"bucket {bucket} k={k} {data} {dim}D {mode} n={len(P)}", flush=True)
     t = zd.ZdTree(dev(P), leaf_size=8, shift_seed=bucket)
-    if mode == "all":
-        assert_rows(t.knn(k), oracle.brute_knn(P, k), f"{data}{dim} all k={k}")
+    root = mode.startswith("root")
+    if mode.endswith("all"):
+        assert_rows(t.knn(k, root=root), oracle.brute_knn(P, k), f"{data}{dim} {mode} k={k}")
     else:
-        assert_rows(t.knn(k, dev(Q)), oracle.brute_knn(P, k, queries=Q), f"{data}{dim} ext k={k}")
+        assert_rows(t.knn(k, dev(Q), root=root), oracle.brute_knn(P, k, queries=Q),
+                    f"{data}{dim} {mode} k={k}")
     t.check()
     t.close()

@@ -7,7 +7,9 @@ of shape (n, d), row-major.
 
 The paper's own generators (uniform cube / square, points on a sphere,
 Plummer, Kuzmin) are not available; these stand in for its uniform 2D / 3D
-sets and its sphere-surface set (Section 4, "Test data").
+sets, its sphere-surface set and its two skewed sets (Section 4, "Test
+data"); the skewed ones are drawn from the published densities of the
+Plummer sphere and the Kuzmin disk by inverting their cumulative mass.
 """
 from __future__ import annotations
 
@@ -56,6 +58,44 @@ def spheres_10m(n: int = 10_000_000, n_spheres: int = 64, noise: float = 1e-4,
     bg = rng.random((nb, 3))
     allp = np.concatenate([pts, bg])
     return allp[rng.permutation(n)]
+
+
+def _unit_directions(rng, n):
+    v = rng.normal(size=(n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def plummer(n: int, seed: int = 0, a: float = 0.01, x_max: float = 0.999,
+            centre=(0.5, 0.5, 0.5)) -> np.ndarray:
+    """Plummer sphere of scale radius a: density proportional to
+    (1 + r^2/a^2)^(-5/2), so the mass inside radius r is the fraction
+    X = r^3 / (r^2 + a^2)^(3/2) and r = a / sqrt(X^(-2/3) - 1).  X is drawn
+    uniform in (0, x_max] (x_max < 1 truncates the unbounded halo), the
+    direction uniform on the sphere."""
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(0.0, x_max, n)
+    X = np.maximum(X, 1e-300)
+    r = a / np.sqrt(X ** (-2.0 / 3.0) - 1.0)
+    return np.asarray(centre)[None, :] + _unit_directions(rng, n) * r[:, None]
+
+
+def kuzmin(n: int, seed: int = 0, a: float = 0.01, x_max: float = 0.999,
+           centre=(0.5, 0.5, 0.5)) -> np.ndarray:
+    """Kuzmin disk of scale length a in the plane z = centre_z: surface
+    density proportional to (R^2 + a^2)^(-3/2), so the mass inside radius R
+    is the fraction X = 1 - a / sqrt(R^2 + a^2) and
+    R = a * sqrt(1 / (1 - X)^2 - 1).  X is drawn uniform in [0, x_max]
+    (x_max < 1 truncates the heavy tail), the angle uniform."""
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(0.0, x_max, n)
+    R = a * np.sqrt(1.0 / (1.0 - X) ** 2 - 1.0)
+    th = rng.uniform(0.0, 2.0 * np.pi, n)
+    c = np.asarray(centre, dtype=np.float64)
+    out = np.empty((n, 3))
+    out[:, 0] = c[0] + R * np.cos(th)
+    out[:, 1] = c[1] + R * np.sin(th)
+    out[:, 2] = c[2]
+    return out
 
 
 def forest_4096_clouds(n_clouds: int = 4096, min_size: int = 1000, max_size: int = 65536,
