@@ -64,7 +64,7 @@ typedef enum {
 } zd_status;
 
 /* largest supported k */
-#define ZD_KMAX 64
+#define ZD_KMAX 100
 
 /* Build parameters.
  *   dim:        2 or 3.

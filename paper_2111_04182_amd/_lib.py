@@ -18,7 +18,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libzd.so")
 
 ZD_OK, ZD_EINVAL, ZD_EBOUNDS, ZD_EID, ZD_ENOMEM, ZD_EDEVICE, ZD_EKMAX, ZD_ELIMIT = range(8)
-ZD_KMAX = 64
+ZD_KMAX = 100
 
 EXPORTED = ("zd_build", "zd_knn", "zd_knn_root", "zd_knn_noalloc", "zd_insert_batch", "zd_delete_batch", "zd_free", "zd_info",
             "zd_check", "zd_set_walk_limit", "zd_export", "zd_knn_backward", "zd_forest_build", "zd_forest_knn", "zd_forest_plan",

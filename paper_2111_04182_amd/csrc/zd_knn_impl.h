@@ -229,12 +229,15 @@ struct Heap {
   }
 };
 
-// For k > 50 the candidate set is a binary max-heap of the k best (d2, id)
-// per lane, kept in LDS (slot-major: slot s of lane l at [s * 64 + l], so a
-// lane's bank never depends on the slot it touches).  Replacing the root and
-// sifting down costs O(log k) instead of the O(k) register shift, and the
-// register file stays small.  The root (the k-th entry) is mirrored in
-// registers for the entry test; the rows are produced by one heap sort.
+// For k > 50 (up to 100, the largest k of the paper's sweep) the candidate
+// set is a binary max-heap of the k best (d2, id) per lane, kept in LDS
+// (slot-major: slot s of lane l at [s * 64 + l], so a lane's bank never
+// depends on the slot it touches): the heap the paper switches to for large
+// k (Section 3.1).  Replacing the root and sifting down costs O(log k)
+// instead of the O(k) register shift, and the register file stays small.
+// The root (the k-th entry) is mirrored in registers for the entry test;
+// the rows are produced by one heap sort.  At k = 100 a wavefront's heaps
+// take 77 KB of LDS, so two wavefronts share a CU.
 template <int K>
 struct LdsHeap {
   double *hd;     // [K][64] this wavefront's distances
@@ -319,7 +322,7 @@ struct LdsHeap {
 // shifts the LDS part of its own lane up by one.  The largest LDS entry is
 // mirrored in registers for the boundary test.  This keeps 2 or 3
 // wavefronts per SIMD where the whole set in LDS (the heap) allowed one, or
-// the whole set in registers two (k = 32).  (k = 51-64
+// the whole set in registers two (k = 32).  (k = 51-100
 // keeps the heap: with R = 24, 40 or 48 the split set measured slower, the
 // larger R overflowing the register file.)
 template <int K, int R_>
@@ -467,13 +470,17 @@ ZD_SPLIT_SET(32, 24)
 ZD_SPLIT_SET(40, 24)
 ZD_SPLIT_SET(50, 32)
 #undef ZD_SPLIT_SET
-template <>
-struct HeapFor<64> {
-  using type = LdsHeap<64>;
-  static constexpr int lds_slots = 64;
+template <int K>
+struct HeapFor_LdsHeap {
+  using type = LdsHeap<K>;
+  static constexpr int lds_slots = K;
   static constexpr bool shared_prescore = true;
   static constexpr bool sorted_fill = false;
 };
+template <>
+struct HeapFor<64> : HeapFor_LdsHeap<64> {};
+template <>
+struct HeapFor<100> : HeapFor_LdsHeap<100> {};
 
 // withinBox(C, p, -r) of Algorithm 3, squared: p in the box and every face
 // strictly farther than the k-th d2 (never true while N holds fewer than k,
@@ -1057,13 +1064,13 @@ hipError_t launch_knn_ext(const TreeView &t, const double *q, const uint64_t *qk
 
 // K buckets: a k between two buckets runs in the larger one (the padding
 // slots cost registers, not correctness)
-#define ZD_FOR_EACH_K(X) X(1) X(2) X(4) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(50) X(64)
+#define ZD_FOR_EACH_K(X) X(1) X(2) X(4) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(50) X(64) X(100)
 
 inline int k_bucket(int k) {
-  const int b[] = {1, 2, 4, 8, 10, 12, 16, 20, 24, 32, 40, 50, 64};
+  const int b[] = {1, 2, 4, 8, 10, 12, 16, 20, 24, 32, 40, 50, 64, 100};
   for (int x : b)
     if (k <= x) return x;
-  return 64;
+  return 100;
 }
 
 }  // namespace zd

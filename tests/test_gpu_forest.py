@@ -58,7 +58,7 @@ def same(got, want, what):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("k", [1, 8, 16, 33])
+@pytest.mark.parametrize("k", [1, 8, 16, 33, 90])
 def test_forest_rows_match_per_cloud_oracle(dim, k):
     P, off = mixed_clouds(10 + dim, dim)
     f = zd.ZdForest(dev(P), off, leaf_size=16, shift_seed=3)

@@ -228,8 +228,21 @@ def test_invalid_arguments():
             zd.ZdTree(P, query_waves=w)
     g = zd.ZdTree(P, 4)
     with pytest.raises(zd.ZdError) as e:
-        g.knn(65)
+        g.knn(zd.ZD_KMAX + 1)
     assert e.value.code == 6
+    g.close()
+
+
+@pytest.mark.parametrize("k", [65, 80, 100])
+def test_large_k_matches_oracle(k):
+    # the paper sweeps k up to 100 (Fig. 3(e)); 65-100 run in the LDS heap
+    P = W.clustered_small(9000, 3, 31)
+    Q = W.uniform(1500, 3, 32)
+    g = zd.ZdTree(dev(P), leaf_size=24, shift_seed=8)
+    assert_same_rows(g.knn(k), oracle.brute_knn(P, k), f"all k={k}")
+    assert_same_rows(g.knn(k, dev(Q)), oracle.brute_knn(P, k, queries=Q), f"ext k={k}")
+    assert_same_rows(g.knn(k, root=True), oracle.brute_knn(P, k), f"root k={k}")
+    g.check()
     g.close()
 
 
