@@ -158,7 +158,9 @@ ZD_API zd_status zd_knn_root(zd_tree tree, const double *q_xyz, int64_t m, int32
  *     32 MiB device array per GPU, held until the process ends; at most
  *     2^20 = 1,048,576 queries per call, otherwise ZD_ELIMIT before anything
  *     is enqueued.  All-points rows (q_xyz == NULL) need no scratch and take
- *     any size zd_knn takes.
+ *     any size zd_knn takes, except that points placed by small inserts
+ *     not yet merged (see zd_insert_batch) answer through the same scratch:
+ *     at most 2^20 of them, otherwise ZD_ELIMIT.
  *   - Every call on one GPU shares that GPU's array: calls that overlap in
  *     time on one GPU (two host threads, or two streams not ordered by the
  *     caller) race on it and may return wrong rows.  Order them.
@@ -171,10 +173,19 @@ ZD_API zd_status zd_knn_noalloc(zd_tree tree, const double *q_xyz, int64_t m, in
 
 /* Batch insertion (Algorithm 4).  The m new points get ids id_capacity,
  * id_capacity + 1, ...; the id capacity grows by m.
+ * A small batch (m <= max(64, n/64)) is applied in place when it can be, as
+ * Algorithm 4 does it: each point descends by its key bits to its leaf, is
+ * appended to that leaf (up to 8 such points per leaf, kept beside the
+ * Morton-ordered array), and the boxes on its path are expanded; no array
+ * of the tree is rewritten.  The tree then departs from its canonical shape
+ * only where the paper's would split a leaf or an edge; queries stay exact.
+ * The canonical shape (a fresh build of the live points) returns with the
+ * next batch that does not fit in place, zd_info or zd_export.
  *   xyz: (device) SoA [dim][m].  out_new_ids: (device) [m] or NULL.
  * The batch is all-or-nothing: if any point lies outside the declared box
- * the call returns ZD_EBOUNDS and the tree is unchanged.  Afterwards the tree
- * equals a fresh build of the live points (same box and shift).
+ * the call returns ZD_EBOUNDS and the tree is unchanged.  The rows of every
+ * query afterwards are those of a fresh build of the live points (same box
+ * and shift).
  * Synchronises `stream` (to validate the batch).  Updates need exclusive
  * access to the tree.
  * Errors: ZD_EINVAL (also when the live points would exceed 2^30 - 1 or the
@@ -184,9 +195,14 @@ ZD_API zd_status zd_insert_batch(zd_tree tree, const double *xyz, int64_t m,
 
 /* Batch deletion (Section 2, "Batch-dynamic updates").
  *   ids: (device) [m] int32 ids to delete.
+ * A small batch (m <= max(16, n/16), or any batch while small batches are
+ * pending) leaves each deleted point's slot in place, marked dead, so no
+ * array is rewritten; past that bound on dead slots, or on zd_info or
+ * zd_export, the tree is rebuilt from the live points.
  * All-or-nothing: an id out of range, already deleted, or repeated in the
  * batch gives ZD_EID with the tree unchanged.  Afterwards the tree equals a
- * fresh build of the live points.  Synchronises `stream`.
+ * fresh build of the live points (immediately for a large batch, else at
+ * the next canonicalisation).  Synchronises `stream`.
  * Errors: ZD_EINVAL, ZD_EID, ZD_ENOMEM, ZD_EDEVICE. */
 ZD_API zd_status zd_delete_batch(zd_tree tree, const int32_t *ids, int64_t m,
                           void *stream);
@@ -204,6 +220,13 @@ ZD_API zd_status zd_free(zd_tree tree);
  * Errors: ZD_EINVAL (NULL tree), ZD_EDEVICE (a self-check failed, or HIP). */
 ZD_API zd_status zd_info(zd_tree tree, int64_t *n_live, int64_t *id_capacity,
                   int64_t *n_leaves, int64_t *n_internal, int32_t *depth);
+
+/* Small batches applied in place and not yet folded into the canonical
+ * shape: points placed beside the sorted arrays by small inserts since the
+ * last rebuild (some may since have been deleted), and deleted points that
+ * still hold their slot.  Host-side counters: no synchronisation.  Either
+ * pointer may be NULL.  Errors: ZD_EINVAL (NULL tree). */
+ZD_API zd_status zd_pending(zd_tree tree, int64_t *in_place_points, int64_t *dead_slots);
 
 /* Synchronise the tree's stream and run the self-checks: ZD_OK, or
  * ZD_EDEVICE when the build or a search since the last check found the tree

@@ -21,7 +21,7 @@ ZD_OK, ZD_EINVAL, ZD_EBOUNDS, ZD_EID, ZD_ENOMEM, ZD_EDEVICE, ZD_EKMAX, ZD_ELIMIT
 ZD_KMAX = 100
 
 EXPORTED = ("zd_build", "zd_knn", "zd_knn_root", "zd_knn_noalloc", "zd_insert_batch", "zd_delete_batch", "zd_free", "zd_info",
-            "zd_check", "zd_set_walk_limit", "zd_export", "zd_knn_backward", "zd_forest_build", "zd_forest_knn", "zd_forest_plan",
+            "zd_check", "zd_pending", "zd_set_walk_limit", "zd_export", "zd_knn_backward", "zd_forest_build", "zd_forest_knn", "zd_forest_plan",
             "zd_forest_run", "zd_forest_check", "zd_forest_free", "zd_status_str")
 
 
@@ -68,6 +68,8 @@ def lib() -> C.CDLL:
         L.zd_free.argtypes = [vp]
         L.zd_info.restype = C.c_int
         L.zd_info.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.zd_pending.restype = C.c_int
+        L.zd_pending.argtypes = [vp, vp, vp]
         L.zd_check.restype = C.c_int
         L.zd_check.argtypes = [vp]
         L.zd_set_walk_limit.restype = C.c_int
@@ -204,6 +206,12 @@ def zd_info(tree, depth: bool = False) -> dict:
     return out
 
 
+def zd_pending(tree) -> tuple:
+    a, b = C.c_int64(), C.c_int64()
+    _check(lib().zd_pending(tree, C.byref(a), C.byref(b)), "zd_pending")
+    return a.value, b.value
+
+
 def zd_check(tree):
     _check(lib().zd_check(tree), "zd_check")
 
@@ -266,6 +274,11 @@ class ZdTree:
 
     def check(self):
         zd_check(self._h)
+
+    def pending(self) -> tuple:
+        """(points placed in place by small inserts, deleted points holding
+        their slot) since the last rebuild."""
+        return zd_pending(self._h)
 
     def knn(self, k: int, queries: torch.Tensor | None = None, stream=None, root=False):
         """All-points rows (queries None, one row per id) or external queries

@@ -85,6 +85,23 @@ struct zd_tree_s {
   int32_t *mark = nullptr;     // [icap] zero between calls
   int32_t *meta = nullptr;     // [kMetaCount]
   double *root_box = nullptr;  // [6]
+  int64_t live = 0;            // live points (sorted arrays and pool, minus deleted)
+  // Small batches applied in place since the last relink (zd_update.hip):
+  // the side pool of leaf blocks and the count of deleted points that still
+  // hold their slot.
+  struct Pending {
+    int32_t *ovf_blk = nullptr;  // [nleaf] pool block of each leaf, -1: none
+    int32_t *ovf_cnt = nullptr;  // [nleaf] points in it
+    int64_t nleaf = 0;
+    double *pxyz = nullptr;      // [dim][pcap] pool coordinates (NaN: unused or deleted)
+    int32_t *pid = nullptr;      // [pcap]
+    int32_t *blocks = nullptr;   // device count of blocks handed out
+    int64_t pcap = 0;            // pool entries (blocks * kOvfBlock)
+    int64_t nblocks = 0;         // blocks handed out (host mirror)
+    int64_t n_pool = 0;          // points placed in the pool
+    int64_t n_tomb = 0;          // deleted points holding their slot
+    bool any() const { return n_pool > 0 || n_tomb > 0; }
+  } pend;
 
   TreeView view() const {
     TreeView v;
@@ -101,6 +118,13 @@ struct zd_tree_s {
     v.walk_err = meta + kMetaWalkErr;
     v.n = st.n;
     v.walk_limit = walk_limit;
+    const bool pool = pend.n_pool > 0;
+    v.ovf_blk = pool ? pend.ovf_blk : nullptr;
+    v.ovf_cnt = pool ? pend.ovf_cnt : nullptr;
+    v.pX = pend.pxyz;
+    v.pY = pend.pxyz ? pend.pxyz + pend.pcap : nullptr;
+    v.pZ = pend.pxyz && dim == 3 ? pend.pxyz + 2 * pend.pcap : nullptr;
+    v.pid = pend.pid;
     return v;
   }
 
@@ -152,10 +176,23 @@ hipError_t join_query_stream(zd_tree t, hipStream_t s, bool after) {
   return e;
 }
 
+void pending_release(zd_tree t) {
+  hipStream_t s = t->stream;
+  dev_release(t->pend.ovf_blk, s);
+  dev_release(t->pend.ovf_cnt, s);
+  dev_release(t->pend.pxyz, s);
+  dev_release(t->pend.pid, s);
+  dev_release(t->pend.blocks, s);
+  t->pend = zd_tree_s::Pending{};
+}
+
 // Relink the tree over the points of t->st (keys sorted, coordinates and
 // slot map in place).  A forest passes the cloud of every position and the
 // leaf size of every cloud.
 hipError_t relink(zd_tree t, const int32_t *seg = nullptr, const int32_t *seg_leaf = nullptr) {
+  // leaves and nodes are renumbered: the per-leaf state of in-place small
+  // batches goes (every caller has folded their points in, or has none)
+  pending_release(t);
   hipStream_t s = t->stream;
   int32_t *flag = nullptr;
   hipError_t e = dev_alloc_n(&flag, t->st.n, s);
@@ -203,8 +240,10 @@ bool finite3(const double *v, int dim) {
   return true;
 }
 
+
 void destroy(zd_tree t) {
   if (!t) return;
+  pending_release(t);
   hipStream_t s = t->stream;
   store_release(t->st, s);
   dev_release(t->slot_of, s);
@@ -247,6 +286,183 @@ zd_status read_meta(zd_tree t, int32_t *meta) {
 }
 
 constexpr int64_t kMaxIds = (int64_t)INT32_MAX - 1;  // ids are int32, -1 pads
+
+// Fold the small batches applied in place, and an optional batch of new
+// points (ids id_base, id_base + 1, ...), back into the sorted arrays and
+// relink: the tree then equals a fresh build of the live points again.
+// Streaming passes as in an insert: the live sorted points compact in
+// order, the live pool points and the batch are keyed and sorted by
+// (key, id), and the two sorted lists merge.
+hipError_t rebuild_live(zd_tree t, const double *bxyz, int64_t nb, int32_t id_base) {
+  hipStream_t s = t->stream;
+  const int dim = t->dim;
+  zd_tree_s::Pending &pd = t->pend;
+  const int64_t n = t->st.n, np = pd.nblocks * kOvfBlock;
+  // 1. live flags of the sorted slots and pool entries, their positions,
+  // and the counts: all live (total) and live sorted (na)
+  int32_t *scan = nullptr;
+  hipError_t e = dev_alloc_n(&scan, n + np + 1, s);
+  if (e == hipSuccess) e = count_live(t->st.X, n, pd.pxyz, np, scan, scan + n + np, s);
+  int32_t *h = host_flag();
+  int32_t cnt[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(h ? h : cnt, scan + n + np, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && np > 0)
+    e = hipMemcpyAsync(h ? h + 1 : cnt + 1, scan + n, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    dev_release(scan, s);
+    return e;
+  }
+  if (h) {
+    cnt[0] = h[0];
+    cnt[1] = h[1];
+  }
+  const int64_t total = cnt[0], na = np > 0 ? cnt[1] : total;
+  const int64_t ne = total - na + nb, n2 = total + nb;
+  // 2. the compacted sorted points, 3. the extra points sorted by (key, id)
+  uint64_t *ka = nullptr, *ekey = nullptr, *ktmp = nullptr;
+  int32_t *ia = nullptr, *eid = nullptr, *eidx = nullptr, *itmp = nullptr, *mscr = nullptr,
+          *src = nullptr;
+  double *xa = nullptr, *tmp = nullptr;
+  Store next;
+  e = dev_alloc_n(&ka, na, s);
+  if (e == hipSuccess) e = dev_alloc_n(&ia, na, s);
+  if (e == hipSuccess) e = dev_alloc_n(&xa, na * dim, s);
+  if (e == hipSuccess) e = dev_alloc_n(&tmp, ne * dim, s);
+  if (e == hipSuccess) e = dev_alloc_n(&ekey, ne, s);
+  if (e == hipSuccess) e = dev_alloc_n(&eid, ne, s);
+  if (e == hipSuccess) e = dev_alloc_n(&eidx, ne, s);
+  if (e == hipSuccess) e = dev_alloc_n(&ktmp, ne, s);
+  if (e == hipSuccess) e = dev_alloc_n(&itmp, ne, s);
+  if (e == hipSuccess) e = dev_alloc_n(&mscr, 2 * n2, s);
+  if (e == hipSuccess) e = dev_alloc_n(&src, n2, s);
+  if (e == hipSuccess) e = store_alloc(next, n2, dim, s);
+  if (e == hipSuccess)
+    e = fold_main(dim, scan, n, t->st.key, t->st.id, t->st.X, t->st.Y, t->st.Z, ka, ia, xa,
+                  xa + na, dim == 3 ? xa + 2 * na : nullptr, s);
+  if (e == hipSuccess)
+    e = fold_extra(dim, scan, n, np, na, pd.pxyz, pd.pcap, pd.pid, bxyz, nb, id_base, ne, tmp,
+                   eid, s);
+  uint64_t *k2 = nullptr;
+  int32_t *i2 = nullptr;
+  if (e == hipSuccess) e = dev_alloc_n(&k2, ne, s);
+  if (e == hipSuccess) e = dev_alloc_n(&i2, ne, s);
+  if (e == hipSuccess) e = encode_keys(t->geo, tmp, ne, ne, 0, ekey, eidx, s);
+  if (e == hipSuccess) e = sort_key_id(ekey, eid, ne, dim * t->geo.B, ktmp, itmp, k2, i2, s);
+  dev_release(k2, s);
+  dev_release(i2, s);
+  // 4. merge, gather
+  if (e == hipSuccess) e = merge_sorted(ka, ia, na, ekey, eid, ne, mscr, next.key, next.id, src, s);
+  if (e == hipSuccess)
+    e = fold_gather(dim, src, n2, na, xa, xa + na, dim == 3 ? xa + 2 * na : nullptr, pd.pxyz,
+                    pd.pcap, bxyz, nb, id_base, next.id, next.X, next.Y, next.Z, t->slot_of, s);
+  for (void *q : {(void *)scan, (void *)ka, (void *)ia, (void *)xa, (void *)tmp, (void *)ekey,
+                  (void *)eid, (void *)eidx, (void *)ktmp, (void *)itmp, (void *)mscr,
+                  (void *)src})
+    dev_release(q, s);
+  if (e != hipSuccess) {
+    store_release(next, s);
+    return e;
+  }
+  store_release(t->st, s);
+  t->st = next;
+  t->live = n2;
+  return relink(t);  // (releases the pool after the gather, in stream order)
+}
+
+// Most points a small insert may place in the pool at once, and the most
+// deleted points left in their slots before the tree is rebuilt.
+int64_t pool_blocks_for(int64_t n) { return std::max<int64_t>(64, n / 64); }
+int64_t tomb_limit(int64_t n) { return std::max<int64_t>(16, n / 16); }
+
+// Algorithm 4 in place for a small batch (zd_update.hip), in two halves
+// around the one synchronisation of zd_insert_batch.  prepare: key and sort
+// the batch and locate every point's leaf by its key bits, counting the
+// points that cannot join their leaf in place and the leaves that need a
+// pool block (meta[kMetaLocal], meta[kMetaBlocks]); nothing of the tree
+// changes.  commit (after the read): place the points and expand the boxes
+// on their paths.
+struct SmallInsert {
+  uint64_t *bk = nullptr, *bk2 = nullptr;
+  int32_t *bi = nullptr, *bi2 = nullptr, *leaf = nullptr, *path = nullptr, *depth = nullptr;
+};
+
+void small_release(zd_tree t, SmallInsert &w) {
+  hipStream_t s = t->stream;
+  dev_release(w.bk, s);
+  dev_release(w.bi, s);
+  dev_release(w.bk2, s);
+  dev_release(w.bi2, s);
+  dev_release(w.leaf, s);
+  dev_release(w.path, s);
+  dev_release(w.depth, s);
+  w = SmallInsert{};
+}
+
+hipError_t insert_small_prepare(zd_tree t, const double *xyz, int64_t m, SmallInsert &w) {
+  hipStream_t s = t->stream;
+  const int dim = t->dim;
+  zd_tree_s::Pending &pd = t->pend;
+  hipError_t e = hipSuccess;
+  if (!pd.ovf_blk) {
+    // the leaf count of the current tree (its last relink), read with
+    // whatever came before on the stream
+    int32_t I = 0;
+    e = read_i32(t->meta + kMetaInternal, &I, s);
+    if (e != hipSuccess) return e;
+    pd.nleaf = (int64_t)I + 1;
+    pd.pcap = pool_blocks_for(t->st.n) * kOvfBlock;
+    e = dev_alloc_n(&pd.ovf_blk, pd.nleaf, s);
+    if (e == hipSuccess) e = dev_alloc_n(&pd.ovf_cnt, pd.nleaf, s);
+    if (e == hipSuccess) e = dev_alloc_n(&pd.pxyz, pd.pcap * dim, s);
+    if (e == hipSuccess) e = dev_alloc_n(&pd.pid, pd.pcap, s);
+    if (e == hipSuccess) e = dev_alloc_n(&pd.blocks, 1, s);
+    if (e == hipSuccess) e = fill_i32(pd.ovf_blk, -1, pd.nleaf, s);
+    if (e == hipSuccess) e = fill_i32(pd.ovf_cnt, 0, pd.nleaf, s);
+    if (e == hipSuccess) e = fill_f64(pd.pxyz, NAN, pd.pcap * dim, s);
+    if (e == hipSuccess) e = fill_i32(pd.blocks, 0, 1, s);
+    if (e != hipSuccess) return e;
+  }
+  e = dev_alloc_n(&w.bk, m, s);
+  if (e == hipSuccess) e = dev_alloc_n(&w.bi, m, s);
+  if (e == hipSuccess) e = dev_alloc_n(&w.bk2, m, s);
+  if (e == hipSuccess) e = dev_alloc_n(&w.bi2, m, s);
+  if (e == hipSuccess) e = dev_alloc_n(&w.leaf, m, s);
+  if (e == hipSuccess) e = dev_alloc_n(&w.path, m * kMaxPath, s);
+  if (e == hipSuccess) e = dev_alloc_n(&w.depth, m, s);
+  if (e == hipSuccess) e = encode_keys(t->geo, xyz, m, m, (int32_t)t->cap, w.bk, w.bi, s);
+  if (e == hipSuccess)
+    e = m <= kSmallSortKeys ? sort_pairs_small(w.bk, w.bi, m, s)
+                            : radix_sort_pairs(w.bk, w.bi, w.bk2, w.bi2, m, dim * t->geo.B, s);
+  if (e == hipSuccess) e = fill_i32(t->meta + kMetaLocal, 0, 2, s);
+  if (e == hipSuccess)
+    e = insert_in_place_locate(t->st.inode, t->st.key, t->st.leaf_begin, t->meta, w.bk, m,
+                               pd.ovf_blk, pd.ovf_cnt, w.leaf, w.path, w.depth,
+                               t->meta + kMetaLocal, t->meta + kMetaBlocks, s);
+  return e;
+}
+
+bool small_fits(const zd_tree t, const int32_t *meta) {
+  return meta[kMetaLocal] == 0 && t->pend.nblocks + meta[kMetaBlocks] <= t->pend.pcap / kOvfBlock;
+}
+
+hipError_t insert_small_commit(zd_tree t, const double *xyz, int64_t m, const SmallInsert &w,
+                               const int32_t *meta) {
+  hipStream_t s = t->stream;
+  zd_tree_s::Pending &pd = t->pend;
+  hipError_t e = grow_ids(t, t->cap + m);
+  if (e == hipSuccess)
+    e = insert_in_place_commit(t->dim, w.leaf, m, w.path, w.depth, w.bi, xyz, (int32_t)t->cap,
+                               pd.ovf_blk, pd.ovf_cnt, pd.blocks, pd.pxyz, pd.pcap, pd.pid,
+                               t->slot_of, t->st.inode, t->root_box, s);
+  if (e == hipSuccess) {
+    pd.nblocks += meta[kMetaBlocks];
+    pd.n_pool += m;
+    t->live += m;
+    t->cap += m;
+  }
+  return e;
+}
 
 }  // namespace
 
@@ -360,8 +576,18 @@ zd_status zd_build(const zd_params *p, const double *xyz, int64_t n, void *strea
     return to_status(e);
   }
   t->cap = n;
+  t->live = n;
   *out = t;
   return ZD_OK;
+}
+
+// All-points rows of a tree with pending small inserts: the points in the
+// pool answer as queries of their own, their own entry excluded.
+static hipError_t pool_rows(zd_tree t, int k, int32_t *out_ids, double *out_d2, hipStream_t s,
+                            bool root) {
+  if (t->pend.n_pool <= 0) return hipSuccess;
+  return knn_pool_rows(t->dim, t->view(), t->geo, t->pend.pxyz, t->pend.pcap, t->pend.pid,
+                       t->pend.nblocks * kOvfBlock, k, out_ids, out_d2, s, t->qwaves, root);
 }
 
 zd_status zd_knn(zd_tree t, const double *q_xyz, int64_t m, int32_t k, int32_t *out_ids,
@@ -376,9 +602,10 @@ zd_status zd_knn(zd_tree t, const double *q_xyz, int64_t m, int32_t k, int32_t *
   hipError_t e = join_query_stream(t, s, false);
   if (e == hipSuccess && m > 0) {
     if (!q_xyz) {
-      if (t->cap > t->st.n) e = fill_dead_rows(t->slot_of, t->cap, k, out_ids, out_d2, s);
+      if (t->cap > t->live) e = fill_dead_rows(t->slot_of, t->cap, k, out_ids, out_d2, s);
       if (e == hipSuccess)
         e = knn_all_points(t->dim, t->view(), k, out_ids, out_d2, s, t->qwaves);
+      if (e == hipSuccess) e = pool_rows(t, k, out_ids, out_d2, s, false);
     } else {
       e = knn_external(t->dim, t->view(), t->geo, q_xyz, m, k, out_ids, out_d2, s, t->qwaves);
     }
@@ -403,10 +630,11 @@ zd_status zd_knn_root(zd_tree t, const double *q_xyz, int64_t m, int32_t k, int3
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = join_query_stream(t, s, false);
   if (e == hipSuccess && m > 0) {
-    if (!q_xyz && t->cap > t->st.n)
+    if (!q_xyz && t->cap > t->live)
       e = fill_dead_rows(t->slot_of, t->cap, k, out_ids, out_d2, s);
     if (e == hipSuccess)
       e = knn_root_based(t->dim, t->view(), t->geo, q_xyz, m, k, out_ids, out_d2, s, t->qwaves);
+    if (e == hipSuccess && !q_xyz) e = pool_rows(t, k, out_ids, out_d2, s, true);
   }
   if (e == hipSuccess) e = join_query_stream(t, s, true);
   return to_status(e);
@@ -421,20 +649,55 @@ zd_status zd_insert_batch(zd_tree t, const double *xyz, int64_t m, int32_t *out_
   hipStream_t s = (hipStream_t)stream;
   const int dim = t->dim;
   hipError_t e = bind_stream(t, s);
-  // 1. validate the whole batch against the declared box (and read the
-  // tree's error counts with the same synchronisation)
+  // 1. validate the whole batch against the declared box; a small batch is
+  // also keyed, sorted and located in the same pass, so that one
+  // synchronisation reads the box check, the tree's error counts and
+  // whether the batch can go into its leaves in place
+  const bool small = t->st.n > 0 && m <= pool_blocks_for(t->st.n);
+  SmallInsert w;
   int32_t meta[kMetaCount];
   if (e == hipSuccess) e = fill_i32(t->meta + kMetaCheck, 0, 1, s);
   if (e == hipSuccess)
     e = count_outside_box(dim, xyz, m, t->geo.lo, t->hi, t->meta + kMetaCheck, s);
+  if (e == hipSuccess && small) e = insert_small_prepare(t, xyz, m, w);
   if (e != hipSuccess) {
+    small_release(t, w);
     t->broken = true;
     return to_status(e);
   }
   const zd_status ms = read_meta(t, meta);
-  if (ms != ZD_OK) return ms;
-  if (meta[kMetaCheck]) return ZD_EBOUNDS;
-  // 2. key and sort the batch (Algorithm 4 starts from a shifted, sorted batch)
+  if (ms != ZD_OK || meta[kMetaCheck]) {
+    small_release(t, w);
+    return ms != ZD_OK ? ms : ZD_EBOUNDS;
+  }
+  const int32_t first_id = (int32_t)t->cap;
+  // 2a. a small batch goes into its leaves in place (Algorithm 4 without
+  // rewriting the sorted arrays) when every point's leaf has room
+  if (small && small_fits(t, meta)) {
+    e = insert_small_commit(t, xyz, m, w, meta);
+    small_release(t, w);
+    if (e == hipSuccess && out_new_ids) e = iota_i32(out_new_ids, first_id, m, s);
+    if (e != hipSuccess) {
+      t->broken = true;
+      return to_status(e);
+    }
+    return ZD_OK;
+  }
+  small_release(t, w);
+  // 2b. with small batches pending, rebuild from the live points and the batch
+  if (t->pend.any()) {
+    e = grow_ids(t, t->cap + m);
+    if (e == hipSuccess) e = rebuild_live(t, xyz, m, first_id);
+    if (e == hipSuccess && out_new_ids) e = iota_i32(out_new_ids, first_id, m, s);
+    if (e != hipSuccess) {
+      t->broken = true;
+      return to_status(e);
+    }
+    t->cap += m;
+    return ZD_OK;
+  }
+  // 2c. key and sort the batch (Algorithm 4 starts from a shifted, sorted
+  // batch) and merge it into the sorted points
   const int64_t n = t->st.n, n2 = n + m;
   uint64_t *bk = nullptr, *bk2 = nullptr;
   int32_t *bi = nullptr, *bi2 = nullptr, *src = nullptr, *scratch = nullptr;
@@ -469,6 +732,7 @@ zd_status zd_insert_batch(zd_tree t, const double *xyz, int64_t m, int32_t *out_
     store_release(t->st, s);
     t->st = next;
     t->cap += m;
+    t->live += m;
     e = relink(t);
   } else {
     store_release(next, s);
@@ -485,7 +749,7 @@ zd_status zd_delete_batch(zd_tree t, const int32_t *ids, int64_t m, void *stream
   if (t->broken) return ZD_EDEVICE;
   if (m == 0) return ZD_OK;
   if (!ids) return ZD_EINVAL;
-  if (m > t->st.n) return ZD_EID;
+  if (m > t->live) return ZD_EID;
   hipStream_t s = (hipStream_t)stream;
   const int dim = t->dim;
   hipError_t e = bind_stream(t, s);
@@ -508,7 +772,23 @@ zd_status zd_delete_batch(zd_tree t, const int32_t *ids, int64_t m, void *stream
     return to_status(e);
   }
   if (bad) return ZD_EID;
-  // 2. remove, 3. compact the survivors in Morton order, 4. relink
+  // 2a. a small batch (or any batch while small batches are pending) leaves
+  // its points' slots in place, with a NaN coordinate; past the bound on
+  // such slots the tree is rebuilt from the live points
+  if (t->pend.any() || m <= tomb_limit(t->st.n)) {
+    e = tombstone_ids(ids, m, t->slot_of, t->mark, t->st.X, t->pend.pxyz, s);
+    if (e == hipSuccess) {
+      t->live -= m;
+      t->pend.n_tomb += m;
+      if (t->pend.n_tomb > tomb_limit(t->st.n)) e = rebuild_live(t, nullptr, 0, 0);
+    }
+    if (e != hipSuccess) {
+      t->broken = true;
+      return to_status(e);
+    }
+    return ZD_OK;
+  }
+  // 2b. remove, 3. compact the survivors in Morton order, 4. relink
   const int64_t n = t->st.n, n2 = n - m;
   int32_t *dead = nullptr, *scan = nullptr;
   Store next;
@@ -531,10 +811,22 @@ zd_status zd_delete_batch(zd_tree t, const int32_t *ids, int64_t m, void *stream
   if (e == hipSuccess) {
     store_release(t->st, s);
     t->st = next;
+    t->live -= m;
     e = relink(t);
   } else {
     store_release(next, s);
   }
+  if (e != hipSuccess) {
+    t->broken = true;
+    return to_status(e);
+  }
+  return ZD_OK;
+}
+
+// Bring a tree with pending small batches back to its canonical shape.
+static zd_status canonical(zd_tree t) {
+  if (!t->pend.any()) return ZD_OK;
+  hipError_t e = rebuild_live(t, nullptr, 0, 0);
   if (e != hipSuccess) {
     t->broken = true;
     return to_status(e);
@@ -551,8 +843,10 @@ zd_status zd_info(zd_tree t, int64_t *n_live, int64_t *id_capacity, int64_t *n_l
                   int64_t *n_internal, int32_t *depth) {
   if (!t) return ZD_EINVAL;
   if (t->broken) return ZD_EDEVICE;
+  zd_status st = canonical(t);
+  if (st != ZD_OK) return st;
   int32_t meta[kMetaCount];
-  zd_status st = read_meta(t, meta);
+  st = read_meta(t, meta);
   if (st != ZD_OK) return st;
   const int32_t I = t->st.n > 0 ? meta[kMetaInternal] : 0;
   int32_t dep = 0;
@@ -565,11 +859,18 @@ zd_status zd_info(zd_tree t, int64_t *n_live, int64_t *id_capacity, int64_t *n_l
       return to_status(e);
     }
   }
-  if (n_live) *n_live = t->st.n;
+  if (n_live) *n_live = t->live;
   if (id_capacity) *id_capacity = t->cap;
   if (n_leaves) *n_leaves = t->st.n > 0 ? (int64_t)I + 1 : 0;
   if (n_internal) *n_internal = I;
   if (depth) *depth = dep;
+  return ZD_OK;
+}
+
+zd_status zd_pending(zd_tree t, int64_t *in_place_points, int64_t *dead_slots) {
+  if (!t) return ZD_EINVAL;
+  if (in_place_points) *in_place_points = t->pend.n_pool;
+  if (dead_slots) *dead_slots = t->pend.n_tomb;
   return ZD_OK;
 }
 
@@ -599,9 +900,11 @@ zd_status zd_export(zd_tree t, uint64_t *keys, int32_t *ids, int64_t *leaf_count
     }
   if (shift_out)
     for (int c = 0; c < dim; ++c) shift_out[c] = t->geo.shift[c];
+  if (t->broken) return ZD_EDEVICE;
+  const zd_status cs = canonical(t);
+  if (cs != ZD_OK) return cs;
   const int64_t n = t->st.n;
   if (n == 0) return ZD_OK;
-  if (t->broken) return ZD_EDEVICE;
   hipStream_t s = t->stream;
   int32_t meta[kMetaCount];
   const zd_status ms = read_meta(t, meta);
@@ -727,14 +1030,28 @@ zd_status zd_knn_noalloc(zd_tree t, const double *q_xyz, int64_t m, int32_t k, i
   if (!q_xyz && m != t->cap) return ZD_EINVAL;
   if (q_xyz && m > kNoAllocMaxQueries) return ZD_ELIMIT;
   if (q_xyz && noalloc_need(m) > kNoAllocScratchBytes) return ZD_ELIMIT;
+  const int64_t mp = t->pend.nblocks * kOvfBlock;  // pool entries queried for all-points rows
+  if (!q_xyz && t->pend.n_pool > 0 && (mp > kNoAllocMaxQueries || noalloc_need(mp) > kNoAllocScratchBytes))
+    return ZD_ELIMIT;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipSuccess;
   if (m > 0) {
     if (!q_xyz) {
       // all-points rows use no scratch
-      if (t->cap > t->st.n) e = fill_dead_rows(t->slot_of, t->cap, k, out_ids, out_d2, s);
+      if (t->cap > t->live) e = fill_dead_rows(t->slot_of, t->cap, k, out_ids, out_d2, s);
       if (e == hipSuccess)
         e = knn_all_points(t->dim, t->view(), k, out_ids, out_d2, s, t->qwaves);
+      if (e == hipSuccess && t->pend.n_pool > 0) {
+        // rows of points placed by small inserts: their presort takes scratch
+        void *base = nullptr;
+        e = scratch_on_device(&base);
+        if (e == hipSuccess) {
+          Arena a{static_cast<char *>(base), kNoAllocScratchBytes, 0};
+          arena_activate(&a);
+          e = pool_rows(t, k, out_ids, out_d2, s, false);
+          arena_activate(nullptr);
+        }
+      }
     } else {
       void *base = nullptr;
       e = scratch_on_device(&base);

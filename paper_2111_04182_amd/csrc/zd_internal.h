@@ -72,7 +72,21 @@ struct TreeView {
   int32_t *walk_err;        // &meta[kMetaWalkErr]: counts searches that gave up
   int64_t n;
   int64_t walk_limit;       // steps a search may take; 0: 4n + 256 (never reached)
+  // Points inserted by small batches since the last relink: leaf l holds,
+  // besides its sorted range, ovf_cnt[l] points at pool entries
+  // [ovf_blk[l] * kOvfBlock, + ovf_cnt[l]).  Null when nothing is pending.
+  // Deleted points keep their slot with a NaN x coordinate (a NaN distance
+  // never enters a candidate set, and a NaN query answers nothing).
+  const int32_t *ovf_blk, *ovf_cnt;
+  const double *pX, *pY, *pZ;
+  const int32_t *pid;
 };
+
+// pool entries per leaf block (at most this many small-batch points per leaf
+// before the tree is rebuilt)
+constexpr int kOvfBlock = 16;
+// slot_of values at or above this encode a pool entry (slot - kPoolSlot)
+constexpr int32_t kPoolSlot = int32_t(1) << 30;
 
 // meta[] slots: the internal node count and root of the tree; a status word
 // for the validation of updates; the count of corrupted climbs in the build
@@ -85,6 +99,8 @@ enum {
   kMetaBuildErr = 3,
   kMetaWalkErr = 4,
   kMetaDepth = 5,
+  kMetaLocal = 6,   // small insert: points that cannot join their leaf in place
+  kMetaBlocks = 7,  // small insert: leaves that need a new pool block
   kMetaCount = 8
 };
 
@@ -243,6 +259,11 @@ hipError_t radix_sort_pairs(uint64_t *key, int32_t *val, uint64_t *key_tmp, int3
                             int64_t n, int key_bits, hipStream_t s, const int4 *tiles = nullptr,
                             int ntiles = 0);
 
+// (key, value) pairs sorted by (key, value) in one workgroup, n <=
+// kSmallSortKeys (values distinct)
+constexpr int kSmallSortKeys = 2048;
+hipError_t sort_pairs_small(uint64_t *key, int32_t *val, int64_t n, hipStream_t s);
+
 // Build kernels.  n points sorted by key in (key, id); the tree arrays have
 // room for n leaves and n internal nodes.
 struct BuildBuffers {
@@ -298,6 +319,12 @@ hipError_t knn_external(int dim, const TreeView &t, const Geometry &g, const dou
 hipError_t knn_root_based(int dim, const TreeView &t, const Geometry &g, const double *q,
                           int64_t m, int k, int32_t *out_ids, double *out_d2, hipStream_t s,
                           int query_waves);
+// All-points rows of the pool entries [0, m) (points of small inserts not
+// yet merged into the sorted arrays): each entry queries the tree with
+// itself excluded; rows go to pid[entry].  pxyz is SoA with stride pstride.
+hipError_t knn_pool_rows(int dim, const TreeView &t, const Geometry &g, const double *pxyz,
+                         int64_t pstride, const int32_t *pid, int64_t m, int k, int32_t *out_ids,
+                         double *out_d2, hipStream_t s, int query_waves, bool root);
 hipError_t fill_dead_rows(const int32_t *slot_of, int64_t cap, int k, int32_t *out_ids,
                           double *out_d2, hipStream_t s);
 
@@ -326,5 +353,43 @@ hipError_t compact_live(int dim, const int32_t *dead_slot, int64_t n, int32_t *s
                         const double *Y, const double *Z, uint64_t *key2, int32_t *id2,
                         double *X2, double *Y2, double *Z2, int32_t *slot_of, hipStream_t s);
 hipError_t iota_i32(int32_t *p, int32_t base, int64_t n, hipStream_t s);
+
+// Small batches in place (see zd_update.hip)
+constexpr int kMaxPath = 64;  // internal nodes on a root-to-leaf path of one tree
+hipError_t insert_in_place_locate(const INode *inode, const uint64_t *tkey,
+                                  const int32_t *leaf_begin, const int32_t *meta,
+                                  const uint64_t *bk, int64_t m, const int32_t *ovf_blk,
+                                  const int32_t *ovf_cnt, int32_t *leaf, int32_t *path,
+                                  int32_t *depth, int32_t *local_fail, int32_t *blocks_needed,
+                                  hipStream_t s);
+hipError_t insert_in_place_commit(int dim, const int32_t *leaf, int64_t m, const int32_t *path,
+                                  const int32_t *depth, const int32_t *bi, const double *bxyz,
+                                  int32_t id_base, int32_t *ovf_blk, int32_t *ovf_cnt,
+                                  int32_t *blocks_used, double *pxyz, int64_t pcap, int32_t *pid,
+                                  int32_t *slot_of, INode *inode, double *root_box,
+                                  hipStream_t s);
+hipError_t tombstone_ids(const int32_t *ids, int64_t m, int32_t *slot_of, int32_t *mark,
+                         double *X, double *pX, hipStream_t s);
+// live flags of the sorted slots and the pool entries, scanned (positions
+// in scan_scratch[n + np], the count in *nlive_dev)
+hipError_t count_live(const double *X, int64_t n, const double *pX, int64_t np,
+                      int32_t *scan_scratch, int32_t *nlive_dev, hipStream_t s);
+// Folding pending small batches back into the sorted arrays (zd_update.hip)
+// (key, id) pairs (ids distinct) into (key, id) order; ktmp, itmp, k2, i2:
+// scratch of n entries each
+hipError_t sort_key_id(uint64_t *key, int32_t *id, int64_t n, int key_bits, uint64_t *ktmp,
+                       int32_t *itmp, uint64_t *k2, int32_t *i2, hipStream_t s);
+hipError_t fold_main(int dim, const int32_t *pos, int64_t n, const uint64_t *key,
+                     const int32_t *id, const double *X, const double *Y, const double *Z,
+                     uint64_t *key2, int32_t *id2, double *X2, double *Y2, double *Z2,
+                     hipStream_t s);
+hipError_t fold_extra(int dim, const int32_t *pos, int64_t n, int64_t np, int64_t na,
+                      const double *pxyz, int64_t pcap, const int32_t *pid, const double *bxyz,
+                      int64_t nb, int32_t id_base, int64_t ne, double *out, int32_t *out_id,
+                      hipStream_t s);
+hipError_t fold_gather(int dim, const int32_t *src, int64_t n2, int64_t na, const double *X,
+                       const double *Y, const double *Z, const double *pxyz, int64_t pcap,
+                       const double *bxyz, int64_t nb, int32_t id_base, const int32_t *iout,
+                       double *X2, double *Y2, double *Z2, int32_t *slot_of, hipStream_t s);
 
 }  // namespace zd

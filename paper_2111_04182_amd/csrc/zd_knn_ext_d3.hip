@@ -3,12 +3,12 @@
 
 namespace zd {
 
-hipError_t knn_ext_d3(const TreeView &t, const double *q, const uint64_t *qkey,
+hipError_t knn_ext_d3(const TreeView &t, const double *q, int64_t qs, const uint64_t *qkey,
                       const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
-                      hipStream_t s, int query_waves) {
+                      const int32_t *row_ids, hipStream_t s, int query_waves) {
   switch (k_bucket(k)) {
 #define X(KK) \
-  case KK: return launch_knn_ext<3, KK>(t, q, qkey, order, m, k, ids, d2, s, query_waves);
+  case KK: return launch_knn_ext<3, KK>(t, q, qs, qkey, order, m, k, ids, d2, row_ids, s, query_waves);
     ZD_FOR_EACH_K(X)
 #undef X
   }

@@ -518,7 +518,7 @@ struct Cand {
 };
 
 // The per-lane state of one wavefront's shared search.
-template <int D, int K, bool kExt = false>
+template <int D, int K, bool kExt = false, bool kPool = false>
 struct WaveSearch {
   const TreeView &t;
   Cand *stage;                   // this wavefront's 64-entry LDS slice (candidates)
@@ -527,6 +527,7 @@ struct WaveSearch {
   bool valid;                    // lane holds a query
   int32_t skip_lo, skip_hi;      // sorted positions already scored (all lanes)
   int32_t own_lo, own_n;         // external queries: this lane's scored leaf
+  int32_t own_pool = -1;         // pool entry of this lane's query (never its own neighbour)
   int64_t budget;                // walk bound (never reached on a valid tree)
   bool gave_up = false;          // the walk stopped before it finished
   uint64_t key_ref;              // Morton key of the group's middle query (child order)
@@ -613,9 +614,12 @@ struct WaveSearch {
         j = j >= cnt ? j - cnt : (j < 0 ? j + cnt : j);
         const Cand q = stage[s <= f ? j : 0];
         const double dd = dist2<D>(px, py, pz, q.x, q.y, q.z);
+        // a deleted point still in its slot (NaN) fills as an empty entry:
+        // the network needs ordered values
+        const bool real = s <= f && !isnan(dd);
         if (valid) {
-          h.d[s - 1] = s <= f ? dd : (s <= k ? INFINITY : -INFINITY);
-          h.id[s - 1] = s <= f ? q.id : (s <= k ? INT_MAX : INT_MIN);
+          h.d[s - 1] = real ? dd : (s <= k ? INFINITY : -INFINITY);
+          h.id[s - 1] = real ? q.id : (s <= k ? INT_MAX : INT_MIN);
         }
       }
       h.sort_slots();
@@ -641,7 +645,17 @@ struct WaveSearch {
   __device__ __forceinline__ void scan_leaf(int32_t leaf) {
     const int lane = threadIdx.x & 63;
     const int32_t b = uni(t.leaf_begin[leaf]), e = uni(t.leaf_begin[leaf + 1]);
-    for (int32_t c = b; c < e; c += 64) {
+    // points placed in this leaf by small inserts follow as virtual
+    // positions [e, e + pn) (pool entries pb ...); they are never in the
+    // skip range, and a deleted one has a NaN x and never enters
+    int32_t pn = 0, pb = 0;
+    if constexpr (kPool) {
+      pn = uni(t.ovf_cnt[leaf]);
+      pb = pn > 0 ? uni(t.ovf_blk[leaf]) * kOvfBlock : 0;
+    }
+    const int32_t ev = e + pn;
+    const int32_t skip_end = kPool ? min(skip_hi + 1, e) : skip_hi + 1;
+    for (int32_t c = b; c < ev; c += 64) {
       const int32_t j = c + lane;
       if (j < e) {
         Cand q;
@@ -651,12 +665,21 @@ struct WaveSearch {
         q.id = t.id[j];
         q.pad = 0;
         stage[lane] = q;
+      } else if (kPool && j < ev) {
+        const int32_t x = pb + (j - e);
+        Cand q;
+        q.x = t.pX[x];
+        q.y = t.pY[x];
+        q.z = D == 3 ? t.pZ[x] : 0.0;
+        q.id = t.pid[x];
+        q.pad = 0;
+        stage[lane] = q;
       }
       __builtin_amdgcn_wave_barrier();
-      const int32_t cnt = min(64, e - c);
+      const int32_t cnt = min(64, ev - c);
       // skipped local range [sa, sb); sa = cnt when it is empty
       int32_t sa = max(skip_lo - c, 0);
-      const int32_t sb = min(skip_hi + 1 - c, cnt);
+      const int32_t sb = min(skip_end - c, cnt);
       if (sa >= sb) sa = cnt;
       for (int32_t jj = 0; jj < cnt; ++jj) {
         if (jj == sa) {
@@ -666,8 +689,11 @@ struct WaveSearch {
         const Cand q = stage[jj];
         const double dd = dist2<D>(px, py, pz, q.x, q.y, q.z);
         if constexpr (kExt) {
-          // a point of the lane's own leaf was scored before the walk
-          const bool seen = (uint32_t)(c + jj - own_lo) < (uint32_t)own_n;
+          // a point of the lane's own leaf was scored before the walk; a
+          // pool query never scores its own entry
+          const int32_t pos = c + jj;
+          const bool seen = !kPool || pos < e ? (uint32_t)(pos - own_lo) < (uint32_t)own_n
+                                              : pb + (pos - e) == own_pool;
           h.template offer<true>(seen ? INFINITY : dd, seen ? INT_MAX : q.id);
         } else {
           // (the split shift pays off in the walk for k >= 16)
@@ -796,8 +822,8 @@ int fit_waves(int want) {
   return w;
 }
 
-template <int D, int K, bool E>
-__device__ __forceinline__ void bind_lds(WaveSearch<D, K, E> &s, char *smem, int w) {
+template <int D, int K, bool E, bool P>
+__device__ __forceinline__ void bind_lds(WaveSearch<D, K, E, P> &s, char *smem, int w) {
   char *base = smem + (size_t)w * wave_lds_bytes<K>();
   s.stage = reinterpret_cast<Cand *>(base);
   if constexpr (HeapFor<K>::lds_slots > 0) {
@@ -822,7 +848,7 @@ constexpr int knn_all_min_waves() {
   return K == 10 ? 6 : (K == 12 ? 5 : (K == 20 || K == 24 || K == 32 ? 3 : 1));
 }
 
-template <int D, int K>
+template <int D, int K, bool kPool>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(knn_all_min_waves<K>())))
 k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
                                                  double *__restrict__ out_d2,
@@ -846,12 +872,13 @@ k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
     c_hi = t.n - 1;
   }
   const int64_t i = min(g0 + lane, last);
-  WaveSearch<D, K> s(t, nullptr);
+  WaveSearch<D, K, false, kPool> s(t, nullptr);
   bind_lds(s, smem, w);
-  s.valid = g0 + lane <= last;
   s.px = t.X[i];
   s.py = t.Y[i];
   s.pz = D == 3 ? t.Z[i] : 0.0;
+  // (a point deleted by a small batch keeps its slot with a NaN x: no query)
+  s.valid = g0 + lane <= last && !isnan(s.px);
   s.self = t.id[i];
   const int mid = (int)((last - g0) / 2);
   s.budget = t.walk_limit > 0 ? t.walk_limit : 4 * t.n + 256;
@@ -894,13 +921,14 @@ constexpr int knn_ext_min_waves() {
   return K == 16 ? 4 : (K == 24 || K == 32 ? 3 : 1);
 }
 
-template <int D, int K>
+template <int D, int K, bool kPool>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(knn_ext_min_waves<K>())))
-k_knn_ext(TreeView t, const double *__restrict__ q,
+k_knn_ext(TreeView t, const double *__restrict__ q, int64_t qs,
                                                  const uint64_t *__restrict__ qkey,
                                                  const int32_t *__restrict__ order, int64_t m,
                                                  int k, int32_t *__restrict__ out_ids,
-                                                 double *__restrict__ out_d2) {
+                                                 double *__restrict__ out_d2,
+                                                 const int32_t *__restrict__ row_ids) {
   extern __shared__ __align__(16) char smem[];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -909,12 +937,21 @@ k_knn_ext(TreeView t, const double *__restrict__ q,
   const int64_t last = min(g0 + 63, m - 1);
   const int64_t i = min(g0 + lane, last);
   const int32_t r = order[i];
-  WaveSearch<D, K, true> s(t, nullptr);
+  WaveSearch<D, K, true, kPool> s(t, nullptr);
   bind_lds(s, smem, w);
-  s.valid = g0 + lane <= last;
   s.px = q[r];
-  s.py = q[m + r];
-  s.pz = D == 3 ? q[2 * m + r] : 0.0;
+  s.py = q[qs + r];
+  s.pz = D == 3 ? q[2 * qs + r] : 0.0;
+  s.valid = g0 + lane <= last;
+  // row_ids: the queries are the tree's own pool entries (points of small
+  // inserts): row = the point's id, the entry itself excluded, a deleted
+  // entry (NaN) answers nothing
+  int64_t row = r;
+  if (row_ids) {
+    row = row_ids[r];
+    s.own_pool = r;
+    s.valid = s.valid && !isnan(s.px);
+  }
   s.self = -1;
   const int mid = (int)((last - g0) / 2);
   s.budget = t.walk_limit > 0 ? t.walk_limit : 4 * t.n + 256;
@@ -966,7 +1003,7 @@ k_knn_ext(TreeView t, const double *__restrict__ q,
     s.run_from(node);
     s.report();
   }
-  if (s.valid) s.h.write(k, out_ids + (int64_t)r * k, out_d2 + (int64_t)r * k);
+  if (s.valid) s.h.write(k, out_ids + row * k, out_d2 + row * k);
 }
 
 // Root-based rows (Section 2): Algorithm 2 from the root with an empty
@@ -976,11 +1013,11 @@ k_knn_ext(TreeView t, const double *__restrict__ q,
 // excluded (a one-point "own" range of the external-query scan); otherwise
 // Morton-presorted external queries as in k_knn_ext.  The shared walk is the
 // same as everywhere else; only its start differs.
-template <int D, int K>
+template <int D, int K, bool kPool>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(knn_ext_min_waves<K>())))
-k_knn_root(TreeView t, const double *__restrict__ q, const uint64_t *__restrict__ qkey,
+k_knn_root(TreeView t, const double *__restrict__ q, int64_t qs, const uint64_t *__restrict__ qkey,
            const int32_t *__restrict__ order, int64_t m, int k, int32_t *__restrict__ out_ids,
-           double *__restrict__ out_d2) {
+           double *__restrict__ out_d2, const int32_t *__restrict__ row_ids) {
   extern __shared__ __align__(16) char smem[];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -989,7 +1026,7 @@ k_knn_root(TreeView t, const double *__restrict__ q, const uint64_t *__restrict_
   const int64_t last = min(g0 + 63, m - 1);
   const int64_t i = min(g0 + lane, last);
   const int mid = (int)((last - g0) / 2);
-  WaveSearch<D, K, true> s(t, nullptr);
+  WaveSearch<D, K, true, kPool> s(t, nullptr);
   bind_lds(s, smem, w);
   s.valid = g0 + lane <= last;
   int64_t row;
@@ -997,16 +1034,22 @@ k_knn_root(TreeView t, const double *__restrict__ q, const uint64_t *__restrict_
   if (q) {
     const int32_t r = order[i];
     s.px = q[r];
-    s.py = q[m + r];
-    s.pz = D == 3 ? q[2 * m + r] : 0.0;
+    s.py = q[qs + r];
+    s.pz = D == 3 ? q[2 * qs + r] : 0.0;
     s.own_lo = 0;
     s.own_n = 0;
     row = r;
+    if (row_ids) {  // the tree's pool entries as queries (see k_knn_ext)
+      row = row_ids[r];
+      s.own_pool = r;
+      s.valid = s.valid && !isnan(s.px);
+    }
     kref = qkey[g0 + mid];
   } else {
     s.px = t.X[i];
     s.py = t.Y[i];
     s.pz = D == 3 ? t.Z[i] : 0.0;
+    s.valid = s.valid && !isnan(s.px);
     s.own_lo = (int32_t)i;
     s.own_n = s.valid ? 1 : 0;
     row = t.id[i];
@@ -1031,13 +1074,19 @@ k_knn_root(TreeView t, const double *__restrict__ q, const uint64_t *__restrict_
 }
 
 template <int D, int K>
-hipError_t launch_knn_root(const TreeView &t, const double *q, const uint64_t *qkey,
+hipError_t launch_knn_root(const TreeView &t, const double *q, int64_t qs, const uint64_t *qkey,
                            const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
-                           hipStream_t s, int query_waves) {
+                           const int32_t *row_ids, hipStream_t s, int query_waves) {
   const int64_t waves = (m + 63) / 64;
   const int wpb = fit_waves<K>(query_waves);
-  k_knn_root<D, K><<<(unsigned)((waves + wpb - 1) / wpb), 64 * wpb, wpb * wave_lds_bytes<K>(), s>>>(
-      t, q, qkey, order, m, k, ids, d2);
+  // (the variant that scans leaves' side blocks only while small inserts are pending)
+  const dim3 grid((unsigned)((waves + wpb - 1) / wpb)), block(64 * wpb);
+  if (t.ovf_cnt)
+    k_knn_root<D, K, true><<<grid, block, wpb * wave_lds_bytes<K>(), s>>>(t, q, qs, qkey, order, m,
+                                                                          k, ids, d2, row_ids);
+  else
+    k_knn_root<D, K, false><<<grid, block, wpb * wave_lds_bytes<K>(), s>>>(t, q, qs, qkey, order, m,
+                                                                           k, ids, d2, row_ids);
   return hipGetLastError();
 }
 
@@ -1046,19 +1095,29 @@ hipError_t launch_knn_all(const TreeView &t, int k, int32_t *ids, double *d2, hi
                           const int4 *groups, int64_t ngroups, int query_waves) {
   const int64_t waves = groups ? ngroups : (t.n + 63) / 64;
   const int wpb = fit_waves<K>(query_waves);
-  k_knn_all<D, K><<<(unsigned)((waves + wpb - 1) / wpb), 64 * wpb, wpb * wave_lds_bytes<K>(), s>>>(
-      t, k, ids, d2, groups, ngroups);
+  const dim3 grid((unsigned)((waves + wpb - 1) / wpb)), block(64 * wpb);
+  if (t.ovf_cnt)
+    k_knn_all<D, K, true><<<grid, block, wpb * wave_lds_bytes<K>(), s>>>(t, k, ids, d2, groups,
+                                                                         ngroups);
+  else
+    k_knn_all<D, K, false><<<grid, block, wpb * wave_lds_bytes<K>(), s>>>(t, k, ids, d2, groups,
+                                                                          ngroups);
   return hipGetLastError();
 }
 
 template <int D, int K>
-hipError_t launch_knn_ext(const TreeView &t, const double *q, const uint64_t *qkey,
+hipError_t launch_knn_ext(const TreeView &t, const double *q, int64_t qs, const uint64_t *qkey,
                           const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
-                          hipStream_t s, int query_waves) {
+                          const int32_t *row_ids, hipStream_t s, int query_waves) {
   const int64_t waves = (m + 63) / 64;
   const int wpb = fit_waves<K>(query_waves);
-  k_knn_ext<D, K><<<(unsigned)((waves + wpb - 1) / wpb), 64 * wpb, wpb * wave_lds_bytes<K>(), s>>>(
-      t, q, qkey, order, m, k, ids, d2);
+  const dim3 grid((unsigned)((waves + wpb - 1) / wpb)), block(64 * wpb);
+  if (t.ovf_cnt)
+    k_knn_ext<D, K, true><<<grid, block, wpb * wave_lds_bytes<K>(), s>>>(t, q, qs, qkey, order, m,
+                                                                         k, ids, d2, row_ids);
+  else
+    k_knn_ext<D, K, false><<<grid, block, wpb * wave_lds_bytes<K>(), s>>>(t, q, qs, qkey, order, m,
+                                                                          k, ids, d2, row_ids);
   return hipGetLastError();
 }
 

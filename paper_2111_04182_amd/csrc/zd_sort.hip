@@ -209,3 +209,56 @@ hipError_t radix_sort_pairs(uint64_t *key, int32_t *val, uint64_t *key_tmp, int3
 }
 
 }  // namespace zd
+
+namespace zd {
+
+// A batch of at most kSmallSortKeys pairs sorted by one workgroup in LDS
+// (bitonic sort on (key, value), values distinct, padding above every real
+// pair): one launch instead of the radix sort's three per pass, for the
+// small batches whose cost is launch latency.  With values given in
+// ascending order (batch ids), the order equals a stable sort by key.
+__global__ void __launch_bounds__(1024) k_sort_small(uint64_t *key, int32_t *val, int m, int np2) {
+  __shared__ uint64_t sk[kSmallSortKeys];
+  __shared__ int32_t sv[kSmallSortKeys];
+  // np2: the power of two >= m that the network spans
+  for (int i = threadIdx.x; i < np2; i += blockDim.x) {
+    sk[i] = i < m ? key[i] : ~uint64_t(0);
+    sv[i] = i < m ? val[i] : INT_MAX;
+  }
+  __syncthreads();
+  for (int size = 2; size <= np2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < np2 / 2; i += blockDim.x) {
+        const int a = 2 * stride * (i / stride) + (i % stride);
+        const int b = a + stride;
+        const bool up = (a & size) == 0;
+        const uint64_t ka = sk[a], kb = sk[b];
+        const int32_t va = sv[a], vb = sv[b];
+        const bool b_first = kb < ka || (kb == ka && vb < va);
+        if (b_first == up) {
+          sk[a] = kb;
+          sk[b] = ka;
+          sv[a] = vb;
+          sv[b] = va;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    key[i] = sk[i];
+    val[i] = sv[i];
+  }
+}
+
+hipError_t sort_pairs_small(uint64_t *key, int32_t *val, int64_t n, hipStream_t s) {
+  if (n <= 1) return hipSuccess;
+  if (n > kSmallSortKeys) return hipErrorInvalidValue;
+  int np2 = 2;
+  while (np2 < n) np2 <<= 1;
+  k_sort_small<<<1, np2 / 2 < 1024 ? (np2 / 2 + 63) / 64 * 64 : 1024, 0, s>>>(key, val, (int)n,
+                                                                             np2);
+  return hipGetLastError();
+}
+
+}  // namespace zd

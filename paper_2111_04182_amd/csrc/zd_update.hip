@@ -308,3 +308,392 @@ hipError_t compact_live(int dim, const int32_t *dead_slot, int64_t n, int32_t *s
 }
 
 }  // namespace zd
+
+namespace zd {
+
+// ------------------------------------------------------- small batches --
+//
+// A small batch is applied in place, as Algorithm 4 does it: each inserted
+// point descends by its key bits to the leaf whose cell holds it and is
+// appended there, and the boxes on its path are expanded; a deleted point
+// is removed from its leaf.  With the points stored contiguously in Morton
+// order, "appended" means written to the leaf's block of a side pool
+// (kOvfBlock entries), and "removed" means its x coordinate becomes NaN:
+// a NaN distance never enters a candidate set.  Boxes only ever grow here,
+// so they stay supersets of their points, and every point stays inside the
+// key cell of each node above it, which is what the pruning and the
+// stopping rule of Algorithms 2 and 3 rely on: the rows stay exact.  What
+// this defers is only the canonical shape (leaves past L points, Patricia
+// edge splits, tight boxes, spliced nodes); the library restores it, with
+// a rebuild from the live points, when the side pool or the deleted
+// points pass their bounds, and before the tree is exported.
+
+// Descend by key bits to the leaf (Algorithm 4's descent), recording the
+// path: path[j * kMaxPath + d] = (node << 1) | side taken at depth d.  The
+// pruned tree skips bits where all of a node's points agree, so the key
+// must also agree with them there, or Algorithm 4 would split that edge:
+// it suffices to compare the key with one point of the leaf above the
+// split bit of the leaf's parent (every point of an ancestor shares that
+// leaf point's bits above the ancestor's higher split bit).
+__global__ void k_ins_locate(const INode *__restrict__ inode, const uint64_t *__restrict__ tkey,
+                             const int32_t *__restrict__ leaf_begin, const int32_t *meta,
+                             const uint64_t *__restrict__ bk, int64_t m,
+                             int32_t *__restrict__ leaf_out, int32_t *__restrict__ path,
+                             int32_t *__restrict__ depth_out, int32_t *local_fail) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const uint64_t key = bk[j];
+  int32_t x = meta[kMetaRoot];
+  bool ok = x != kNoRoot;
+  int d = 0, last_bit = 64;
+  for (; ok && x >= 0; ++d) {
+    if (d == kMaxPath) {
+      ok = false;
+      break;
+    }
+    const int bit = inode[x].bit;
+    const int side = (int)((key >> bit) & 1);
+    path[j * kMaxPath + d] = (x << 1) | side;
+    last_bit = bit;
+    x = inode[x].child[side];
+  }
+  if (ok && last_bit < 63 && ((key ^ tkey[leaf_begin[~x]]) >> (last_bit + 1)) != 0) ok = false;
+  leaf_out[j] = ok ? ~x : -1;
+  depth_out[j] = ok ? d : 0;
+  if (!ok) atomicAdd(local_fail, 1);
+}
+
+// One thread per run of batch points bound for one leaf (the batch is
+// sorted by key, and leaves hold consecutive key ranges): the run must fit
+// in the leaf's block; count the leaves that need a new block.
+__global__ void k_ins_runs(const int32_t *__restrict__ leaf, int64_t m,
+                           const int32_t *__restrict__ ovf_blk, const int32_t *__restrict__ ovf_cnt,
+                           int32_t *local_fail, int32_t *blocks_needed) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const int32_t l = leaf[j];
+  if (l < 0 || (j > 0 && leaf[j - 1] == l)) return;
+  int64_t r = 1;
+  while (j + r < m && leaf[j + r] == l) ++r;
+  if (ovf_cnt[l] + r > kOvfBlock) atomicAdd(local_fail, 1);
+  if (ovf_blk[l] < 0) atomicAdd(blocks_needed, 1);
+}
+
+// FP64 atomic min / max in L2 (global_atomic_min_f64 / max_f64 on gfx950;
+// the result is unused, so the climb does not wait for them)
+__device__ __forceinline__ void atomic_min_f64(double *a, double v) {
+  __hip_atomic_fetch_min(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void atomic_max_f64(double *a, double v) {
+  __hip_atomic_fetch_max(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One wavefront per batch point; the wavefronts of run starts place their
+// run: lane 0 takes a block for the leaf if it has none and writes the
+// points (coordinates from the caller's batch, read at id - id_base), ids
+// and slot map; then lane d merges the run's box into the box at depth d
+// of the recorded path (each parent stores its children's boxes; an atomic
+// is issued only where the box grows), all levels at once, and lane 0 into
+// the root box.
+template <int D>
+__global__ void __launch_bounds__(64)
+    k_ins_commit(const int32_t *__restrict__ leaf, int64_t m, const int32_t *__restrict__ path,
+                 const int32_t *__restrict__ depth, const int32_t *__restrict__ bi,
+                 const double *__restrict__ bxyz, int64_t nb, int32_t id_base, int32_t *ovf_blk,
+                 int32_t *ovf_cnt, int32_t *blocks_used, double *pxyz, int64_t pcap,
+                 int32_t *pid, int32_t *slot_of, INode *inode, double *root_box) {
+  const int64_t j = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int32_t l = leaf[j];
+  if (j > 0 && leaf[j - 1] == l) return;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (lane == 0) {
+    int32_t blk = ovf_blk[l];
+    if (blk < 0) {
+      blk = atomicAdd(blocks_used, 1);
+      ovf_blk[l] = blk;
+    }
+    const int32_t c0 = ovf_cnt[l];
+    int64_t r = 0;
+    for (; j + r < m && leaf[j + r] == l; ++r) {
+      const int64_t e = (int64_t)blk * kOvfBlock + c0 + r;
+      const int32_t id = bi[j + r];
+      const int64_t src = (int64_t)id - id_base;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double v = bxyz[c * nb + src];
+        pxyz[c * pcap + e] = v;
+        lo[c] = fmin(lo[c], v);
+        hi[c] = fmax(hi[c], v);
+      }
+      pid[e] = id;
+      slot_of[id] = kPoolSlot + (int32_t)e;
+    }
+    ovf_cnt[l] = c0 + (int32_t)r;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      atomic_min_f64(&root_box[c], lo[c]);
+      atomic_max_f64(&root_box[3 + c], hi[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    lo[c] = __shfl(lo[c], 0, 64);
+    hi[c] = __shfl(hi[c], 0, 64);
+  }
+  if (lane < depth[j]) {
+    const int32_t link = path[j * kMaxPath + lane];
+    INode *P = &inode[link >> 1];
+    const int side = link & 1;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      if (lo[c] < P->lo[side][c]) atomic_min_f64(&P->lo[side][c], lo[c]);
+      if (hi[c] > P->hi[side][c]) atomic_max_f64(&P->hi[side][c], hi[c]);
+    }
+  }
+}
+
+hipError_t insert_in_place_locate(const INode *inode, const uint64_t *tkey,
+                                  const int32_t *leaf_begin, const int32_t *meta,
+                                  const uint64_t *bk, int64_t m, const int32_t *ovf_blk,
+                                  const int32_t *ovf_cnt, int32_t *leaf, int32_t *path,
+                                  int32_t *depth, int32_t *local_fail, int32_t *blocks_needed,
+                                  hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((m + 255) / 256);
+  k_ins_locate<<<grid, 256, 0, s>>>(inode, tkey, leaf_begin, meta, bk, m, leaf, path, depth,
+                                    local_fail);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_ins_runs<<<grid, 256, 0, s>>>(leaf, m, ovf_blk, ovf_cnt, local_fail, blocks_needed);
+  return hipGetLastError();
+}
+
+hipError_t insert_in_place_commit(int dim, const int32_t *leaf, int64_t m, const int32_t *path,
+                                  const int32_t *depth, const int32_t *bi, const double *bxyz,
+                                  int32_t id_base, int32_t *ovf_blk, int32_t *ovf_cnt,
+                                  int32_t *blocks_used, double *pxyz, int64_t pcap, int32_t *pid,
+                                  int32_t *slot_of, INode *inode, double *root_box,
+                                  hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  static_assert(kMaxPath <= 64, "one lane per path level");
+  const unsigned grid = (unsigned)m;
+  if (dim == 3)
+    k_ins_commit<3><<<grid, 64, 0, s>>>(leaf, m, path, depth, bi, bxyz, m, id_base, ovf_blk,
+                                        ovf_cnt, blocks_used, pxyz, pcap, pid, slot_of, inode,
+                                        root_box);
+  else
+    k_ins_commit<2><<<grid, 64, 0, s>>>(leaf, m, path, depth, bi, bxyz, m, id_base, ovf_blk,
+                                        ovf_cnt, blocks_used, pxyz, pcap, pid, slot_of, inode,
+                                        root_box);
+  return hipGetLastError();
+}
+
+// Small deletes: the point keeps its slot (sorted position or pool entry)
+// with a NaN x; its id becomes dead.
+__global__ void k_tombstone(const int32_t *__restrict__ ids, int64_t m, int32_t *slot_of,
+                            int32_t *mark, double *X, double *pX) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const int32_t id = ids[j];
+  const int32_t sl = slot_of[id];
+  if (sl >= kPoolSlot) pX[sl - kPoolSlot] = NAN;
+  else X[sl] = NAN;
+  slot_of[id] = -1;
+  mark[id] = 0;
+}
+
+hipError_t tombstone_ids(const int32_t *ids, int64_t m, int32_t *slot_of, int32_t *mark,
+                         double *X, double *pX, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  k_tombstone<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(ids, m, slot_of, mark, X, pX);
+  return hipGetLastError();
+}
+
+// Live flags of the sorted slots and the pool entries (x not NaN).
+__global__ void k_live_flags(const double *__restrict__ X, int64_t n, const double *__restrict__ pX,
+                             int64_t np, int32_t *__restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n + np) return;
+  const double x = i < n ? X[i] : pX[i - n];
+  flag[i] = isnan(x) ? 0 : 1;
+}
+
+
+
+}  // namespace zd
+
+namespace zd {
+
+// ------------------------------------------------------ folding a pool --
+//
+// The canonical shape back after small batches, in streaming passes: the
+// live sorted points compact in place of order (their keys stay sorted),
+// the live pool points and a new batch are keyed and sorted by (key, id),
+// and the two sorted lists merge as in an insert.
+
+// live sorted points to their compacted positions (pos from count_live)
+template <int D>
+__global__ void k_fold_main(const int32_t *__restrict__ pos, int64_t n,
+                            const uint64_t *__restrict__ key, const int32_t *__restrict__ id,
+                            const double *__restrict__ X, const double *__restrict__ Y,
+                            const double *__restrict__ Z, uint64_t *__restrict__ key2,
+                            int32_t *__restrict__ id2, double *__restrict__ X2,
+                            double *__restrict__ Y2, double *__restrict__ Z2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || isnan(X[i])) return;
+  const int32_t p = pos[i];
+  key2[p] = key[i];
+  id2[p] = id[i];
+  X2[p] = X[i];
+  Y2[p] = Y[i];
+  if (D == 3) Z2[p] = Z[i];
+}
+
+// live pool entries (at pos - na) and the batch (after them): their
+// coordinates, for the keys, and their ids
+template <int D>
+__global__ void k_fold_extra(const int32_t *__restrict__ pos, int64_t n, int64_t np, int64_t na,
+                             const double *__restrict__ pxyz, int64_t pcap,
+                             const int32_t *__restrict__ pid, const double *__restrict__ bxyz,
+                             int64_t nb, int32_t id_base, int64_t ne, double *__restrict__ out,
+                             int32_t *__restrict__ out_id) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < np) {
+    if (isnan(pxyz[i])) return;
+    const int64_t p = pos[n + i] - na;
+#pragma unroll
+    for (int c = 0; c < D; ++c) out[c * ne + p] = pxyz[c * pcap + i];
+    out_id[p] = pid[i];
+  } else if (i < np + nb) {
+    const int64_t b = i - np;
+    const int64_t p = ne - nb + b;
+#pragma unroll
+    for (int c = 0; c < D; ++c) out[c * ne + p] = bxyz[c * nb + b];
+    out_id[p] = id_base + (int32_t)b;
+  }
+}
+
+// coordinates of the merged order: from the compacted sorted points, or
+// for an extra point from the batch (id >= id_base) or its pool entry
+// (found through the slot map before this thread overwrites it)
+template <int D>
+__global__ void k_fold_gather(const int32_t *__restrict__ src, int64_t n2, int64_t na,
+                              const double *__restrict__ X, const double *__restrict__ Y,
+                              const double *__restrict__ Z, const double *__restrict__ pxyz,
+                              int64_t pcap, const double *__restrict__ bxyz, int64_t nb,
+                              int32_t id_base, const int32_t *__restrict__ iout,
+                              double *__restrict__ X2, double *__restrict__ Y2,
+                              double *__restrict__ Z2, int32_t *__restrict__ slot_of) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n2) return;
+  const int64_t sidx = src[p];
+  const int32_t v = iout[p];
+  if (sidx < na) {
+    X2[p] = X[sidx];
+    Y2[p] = Y[sidx];
+    if (D == 3) Z2[p] = Z[sidx];
+  } else if (nb > 0 && v >= id_base) {
+    const int64_t b = (int64_t)v - id_base;
+    X2[p] = bxyz[b];
+    Y2[p] = bxyz[nb + b];
+    if (D == 3) Z2[p] = bxyz[2 * nb + b];
+  } else {
+    const int64_t e = (int64_t)slot_of[v] - kPoolSlot;
+    X2[p] = pxyz[e];
+    Y2[p] = pxyz[pcap + e];
+    if (D == 3) Z2[p] = pxyz[2 * pcap + e];
+  }
+  slot_of[v] = (int32_t)p;
+}
+
+hipError_t count_live(const double *X, int64_t n, const double *pX, int64_t np,
+                      int32_t *scan_scratch, int32_t *nlive_dev, hipStream_t s) {
+  if (n + np <= 0) return fill_i32(nlive_dev, 0, 1, s);
+  k_live_flags<<<(unsigned)((n + np + 255) / 256), 256, 0, s>>>(X, n, pX, np, scan_scratch);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = exclusive_scan_i32(scan_scratch, scan_scratch, n + np, nlive_dev, s);
+  return e;
+}
+
+__global__ void k_id_as_key(const int32_t *__restrict__ id, int64_t n, uint64_t *__restrict__ k) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) k[i] = (uint64_t)(uint32_t)id[i];
+}
+
+__global__ void k_permute_pairs(const int32_t *__restrict__ order, int64_t n,
+                                const uint64_t *__restrict__ key, const int32_t *__restrict__ id,
+                                uint64_t *__restrict__ key2, int32_t *__restrict__ id2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key2[i] = key[order[i]];
+  id2[i] = id[order[i]];
+}
+
+// (key, id) pairs, ids distinct, into (key, id) order: by id first, then a
+// stable sort by key (one workgroup when they are few)
+hipError_t sort_key_id(uint64_t *key, int32_t *id, int64_t n, int key_bits, uint64_t *ktmp,
+                       int32_t *itmp, uint64_t *k2, int32_t *i2, hipStream_t s) {
+  if (n <= 1) return hipSuccess;
+  if (n <= kSmallSortKeys) return sort_pairs_small(key, id, n, s);
+  // ids as keys (31 bits), the positions as values
+  hipError_t e = hipMemcpyAsync(itmp, id, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = iota_i32(i2, 0, n, s);
+  if (e != hipSuccess) return e;
+  k_id_as_key<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(itmp, n, k2);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = radix_sort_pairs(k2, i2, ktmp, itmp, n, 32, s);
+  if (e != hipSuccess) return e;
+  k_permute_pairs<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(i2, n, key, id, k2, itmp);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(key, k2, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(id, itmp, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = radix_sort_pairs(key, id, ktmp, itmp, n, key_bits, s);
+  return e;
+}
+
+hipError_t fold_main(int dim, const int32_t *pos, int64_t n, const uint64_t *key,
+                     const int32_t *id, const double *X, const double *Y, const double *Z,
+                     uint64_t *key2, int32_t *id2, double *X2, double *Y2, double *Z2,
+                     hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  if (dim == 3)
+    k_fold_main<3><<<grid, 256, 0, s>>>(pos, n, key, id, X, Y, Z, key2, id2, X2, Y2, Z2);
+  else
+    k_fold_main<2><<<grid, 256, 0, s>>>(pos, n, key, id, X, Y, Z, key2, id2, X2, Y2, Z2);
+  return hipGetLastError();
+}
+
+hipError_t fold_extra(int dim, const int32_t *pos, int64_t n, int64_t np, int64_t na,
+                      const double *pxyz, int64_t pcap, const int32_t *pid, const double *bxyz,
+                      int64_t nb, int32_t id_base, int64_t ne, double *out, int32_t *out_id,
+                      hipStream_t s) {
+  if (np + nb <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((np + nb + 255) / 256);
+  if (dim == 3)
+    k_fold_extra<3><<<grid, 256, 0, s>>>(pos, n, np, na, pxyz, pcap, pid, bxyz, nb, id_base, ne,
+                                         out, out_id);
+  else
+    k_fold_extra<2><<<grid, 256, 0, s>>>(pos, n, np, na, pxyz, pcap, pid, bxyz, nb, id_base, ne,
+                                         out, out_id);
+  return hipGetLastError();
+}
+
+hipError_t fold_gather(int dim, const int32_t *src, int64_t n2, int64_t na, const double *X,
+                       const double *Y, const double *Z, const double *pxyz, int64_t pcap,
+                       const double *bxyz, int64_t nb, int32_t id_base, const int32_t *iout,
+                       double *X2, double *Y2, double *Z2, int32_t *slot_of, hipStream_t s) {
+  if (n2 <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((n2 + 255) / 256);
+  if (dim == 3)
+    k_fold_gather<3><<<grid, 256, 0, s>>>(src, n2, na, X, Y, Z, pxyz, pcap, bxyz, nb, id_base,
+                                          iout, X2, Y2, Z2, slot_of);
+  else
+    k_fold_gather<2><<<grid, 256, 0, s>>>(src, n2, na, X, Y, Z, pxyz, pcap, bxyz, nb, id_base,
+                                          iout, X2, Y2, Z2, slot_of);
+  return hipGetLastError();
+}
+
+}  // namespace zd

@@ -64,6 +64,7 @@ def test_argument_errors_need_no_device(L):
     assert L.zd_delete_batch(None, None, 1, None) == B.ZD_EINVAL
     assert L.zd_info(None, None, None, None, None, None) == B.ZD_EINVAL
     assert L.zd_check(None) == B.ZD_EINVAL
+    assert L.zd_pending(None, None, None) == B.ZD_EINVAL
     assert L.zd_set_walk_limit(None, 0) == B.ZD_EINVAL
     assert L.zd_free(None) == B.ZD_OK
     assert L.zd_knn_backward(4, None, 0, 0, 1, None, None, None, None) == B.ZD_EINVAL
