@@ -100,8 +100,8 @@ PAPER_BUILD_QUERY_K10_QPS = 10_000_000 / 0.453  # CPU context only (144 threads)
 # They describe the kernel sources whose code (comments stripped) has this
 # sha1 only; after any change to that code the figure is reported as null
 # until the counters are taken again.
-KNN_TRAFFIC = {"sources_sha1": "10adc362418a650a47a8ed0f428261299de96575",
-               "fetch_bytes": 2.275e9, "write_bytes": 2.353e9}
+KNN_TRAFFIC = {"sources_sha1": "80f3d8939830036e09a0745bd33546eeef358cbe",
+               "fetch_bytes": 2.017e+09, "write_bytes": 2.292e+09}
 TRAFFIC_LEAF = 24  # leaf size of the profiled run
 KNN_SOURCES = ("paper_2111_04182_amd/csrc/zd_knn_impl.h", "paper_2111_04182_amd/csrc/zd_internal.h",
                "paper_2111_04182_amd/csrc/zd_sortnet.h", "paper_2111_04182_amd/csrc/zd_knn_all_d3.hip")
@@ -360,6 +360,7 @@ def main():
         tree.close()
         legs = [("external_1M_k10",
                  lambda: leg_external(xyz, L, args.steps, tr if not args.no_cpu else None)),
+                ("small_updates", lambda: leg_small_updates(P, L)),
                 ("spheres_10M", lambda: leg_spheres(args.leaf, args.steps)),
                 ("skewed_10M", lambda: leg_skewed(args.leaf, args.steps)),
                 ("forest_4096", lambda: leg_forest(args.steps)),
@@ -419,6 +420,62 @@ def leg_external(xyz, L, steps, oracle_tree=None, m=1_000_000, k=10):
         res["verified"] = _rows_equal(out, oracle_tree.knn(Q[sel], k), torch.from_numpy(sel).cuda())
     tree.close()
     return res
+
+
+def leg_small_updates(P, leaf, batches=(1, 10, 100, 1000, 10000), reps=6, verify=200):
+    """Latency of one insert and one delete call for small batches into
+    trees of 1M (the first 1M points) and 10M points (Algorithm 4 applied in
+    place: Fig. 4's small-batch end).  Each rep inserts m new uniform points
+    and then deletes m random live ids (so n stays put); the median over
+    reps 2..reps is reported, with the in-place state left pending.  Rows
+    of sampled live points are checked against brute force at the end."""
+    import torch
+    import oracle
+    import paper_2111_04182_amd as zd
+    import workloads as W
+    out = {}
+    for n in (1_000_000, P.shape[0]):
+        base = P[:n]
+        t = zd.ZdTree(zd.soa(torch.from_numpy(base)), leaf, box=W.UNIT3, shift_seed=0)
+        allp = [base]
+        live = np.ones(n, dtype=bool)
+        rng = np.random.default_rng(7)
+        res = {}
+        for m in batches:
+            ti, td = [], []
+            for rep in range(reps):
+                B = rng.random((m, 3))
+                Bx = zd.soa(torch.from_numpy(B))
+                live = np.concatenate([live, np.ones(m, dtype=bool)])
+                D = rng.choice(np.flatnonzero(live), m, replace=False).astype(np.int32)
+                Dt = torch.from_numpy(D).cuda()
+                torch.cuda.synchronize()
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                e[0].record()
+                t.insert(Bx)
+                e[1].record()
+                t.delete(Dt)
+                e[2].record()
+                torch.cuda.synchronize()
+                allp.append(B)
+                live[D] = False
+                if rep:
+                    ti.append(e[0].elapsed_time(e[1]))
+                    td.append(e[1].elapsed_time(e[2]))
+            res[str(m)] = {"insert_us": float(np.median(ti)) * 1e3,
+                           "delete_us": float(np.median(td)) * 1e3,
+                           "pending_after": list(t.pending())}
+        if verify:
+            pts = np.concatenate(allp)
+            sel = rng.choice(np.flatnonzero(live), verify, replace=False)
+            got = t.knn(10)
+            want = oracle.brute_knn(pts, 10, live=live, qids=sel)
+            res["verified_rows"] = int(verify)
+            res["verified"] = _rows_equal(got, want, torch.from_numpy(sel).cuda())
+        t.check()
+        t.close()
+        out[f"n={n}"] = res
+    return out
 
 
 def leg_spheres(leaf, steps, verify=50):
