@@ -266,6 +266,16 @@ ZD_API zd_status zd_knn_backward(int32_t dim, const double *xyz, int64_t stride,
                           const double *grad_d2, double *grad_xyz,
                           void *stream);
 
+/* zd_knn_backward without atomics: the edges are sorted by neighbour once
+ * (a radix sort of rows * k keys), and one thread per point sums its own
+ * terms and then the terms of the rows that chose it, in a fixed order, so
+ * every run returns the same bits.  Same arguments and errors as
+ * zd_knn_backward, plus ZD_EINVAL when stride or rows * k exceeds 2^31 - 2.
+ * Scratch: about 24 bytes per edge, from the library's device cache. */
+ZD_API zd_status zd_knn_backward_det(int32_t dim, const double *xyz, int64_t stride,
+                                     int64_t rows, int32_t k, const int32_t *ids,
+                                     const double *grad_d2, double *grad_xyz, void *stream);
+
 /* Batched forest: C independent point clouds answered in one pass (an
  * addition beyond the paper, which builds one tree).  Cloud c is points
  * [offsets[c], offsets[c+1]) of xyz; point i keeps id i.  Every cloud gets

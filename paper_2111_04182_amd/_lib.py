@@ -21,7 +21,7 @@ ZD_OK, ZD_EINVAL, ZD_EBOUNDS, ZD_EID, ZD_ENOMEM, ZD_EDEVICE, ZD_EKMAX, ZD_ELIMIT
 ZD_KMAX = 100
 
 EXPORTED = ("zd_build", "zd_knn", "zd_knn_root", "zd_knn_noalloc", "zd_insert_batch", "zd_delete_batch", "zd_free", "zd_info",
-            "zd_check", "zd_pending", "zd_set_walk_limit", "zd_export", "zd_knn_backward", "zd_forest_build", "zd_forest_knn", "zd_forest_plan",
+            "zd_check", "zd_pending", "zd_set_walk_limit", "zd_export", "zd_knn_backward", "zd_knn_backward_det", "zd_forest_build", "zd_forest_knn", "zd_forest_plan",
             "zd_forest_run", "zd_forest_check", "zd_forest_free", "zd_status_str")
 
 
@@ -76,6 +76,8 @@ def lib() -> C.CDLL:
         L.zd_set_walk_limit.argtypes = [vp, i64]
         L.zd_export.restype = C.c_int
         L.zd_export.argtypes = [vp] * 11
+        L.zd_knn_backward_det.restype = C.c_int
+        L.zd_knn_backward_det.argtypes = [i32, vp, i64, i64, i32, vp, vp, vp, vp]
         L.zd_knn_backward.restype = C.c_int
         L.zd_knn_backward.argtypes = [i32, vp, i64, i64, i32, vp, vp, vp, vp]
         L.zd_forest_build.restype = C.c_int
@@ -236,9 +238,11 @@ def zd_export(tree, dim: int) -> dict:
 
 
 def zd_knn_backward(xyz: torch.Tensor, ids: torch.Tensor, grad_d2: torch.Tensor,
-                    grad_xyz: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+                    grad_xyz: torch.Tensor | None = None, stream=None,
+                    deterministic: bool = False) -> torch.Tensor:
     """Gradient of sum(grad_d2 * d2) w.r.t. SoA points xyz (d, n) for the fixed
-    neighbour table ids [rows, k] (row r = point r)."""
+    neighbour table ids [rows, k] (row r = point r).  deterministic=True
+    sums in a fixed order without atomics (the same bits on every run)."""
     _check_soa(xyz)
     dim, n = xyz.shape
     rows, k = ids.shape
@@ -246,8 +250,9 @@ def zd_knn_backward(xyz: torch.Tensor, ids: torch.Tensor, grad_d2: torch.Tensor,
         grad_xyz = torch.empty_like(xyz)
     ids = ids.contiguous()
     grad_d2 = grad_d2.to(torch.float64).contiguous()
-    _check(lib().zd_knn_backward(dim, _dptr(xyz), n, rows, k, _dptr(ids), _dptr(grad_d2),
-                                 _dptr(grad_xyz), _stream(stream)), "zd_knn_backward")
+    fn = lib().zd_knn_backward_det if deterministic else lib().zd_knn_backward
+    _check(fn(dim, _dptr(xyz), n, rows, k, _dptr(ids), _dptr(grad_d2), _dptr(grad_xyz),
+              _stream(stream)), "zd_knn_backward")
     return grad_xyz
 
 

@@ -18,10 +18,11 @@ from ._lib import ZdTree, zd_knn_backward
 
 class ZdKnnSqDist(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, xyz: torch.Tensor, tree: ZdTree, k: int):
+    def forward(ctx, xyz: torch.Tensor, tree: ZdTree, k: int, deterministic: bool = False):
         ids, d2 = tree.knn(k)
         ctx.save_for_backward(xyz, ids)
         ctx.mark_non_differentiable(ids)
+        ctx.deterministic = deterministic
         return d2, ids
 
     @staticmethod
@@ -29,10 +30,11 @@ class ZdKnnSqDist(torch.autograd.Function):
         xyz, ids = ctx.saved_tensors
         g = torch.zeros(ids.shape, dtype=torch.float64, device=xyz.device) if grad_d2 is None \
             else grad_d2.contiguous()
-        grad = zd_knn_backward(xyz.detach(), ids, g)
-        return grad, None, None
+        grad = zd_knn_backward(xyz.detach(), ids, g, deterministic=ctx.deterministic)
+        return grad, None, None, None
 
 
-def knn_sq_dist(xyz: torch.Tensor, tree: ZdTree, k: int):
-    """Functional form of ZdKnnSqDist."""
-    return ZdKnnSqDist.apply(xyz, tree, k)
+def knn_sq_dist(xyz: torch.Tensor, tree: ZdTree, k: int, deterministic: bool = False):
+    """Functional form of ZdKnnSqDist.  deterministic=True makes the backward
+    sum in a fixed order without atomics (the same bits on every run)."""
+    return ZdKnnSqDist.apply(xyz, tree, k, deterministic)

@@ -963,6 +963,17 @@ zd_status zd_knn_backward(int32_t dim, const double *xyz, int64_t stride, int64_
       knn_backward(dim, xyz, stride, rows, k, ids, grad_d2, grad_xyz, (hipStream_t)stream));
 }
 
+zd_status zd_knn_backward_det(int32_t dim, const double *xyz, int64_t stride, int64_t rows,
+                              int32_t k, const int32_t *ids, const double *grad_d2,
+                              double *grad_xyz, void *stream) {
+  if ((dim != 2 && dim != 3) || stride < 0 || rows < 0 || rows > stride || k < 1) return ZD_EINVAL;
+  if (stride > kMaxIds || rows * (int64_t)k > kMaxIds) return ZD_EINVAL;
+  if (stride > 0 && (!xyz || !grad_xyz)) return ZD_EINVAL;
+  if (rows > 0 && (!ids || !grad_d2)) return ZD_EINVAL;
+  return to_status(
+      knn_backward_det(dim, xyz, stride, rows, k, ids, grad_d2, grad_xyz, (hipStream_t)stream));
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------

@@ -49,3 +49,114 @@ hipError_t knn_backward(int dim, const double *xyz, int64_t stride, int64_t rows
 }
 
 }  // namespace zd
+
+namespace zd {
+
+// ---------------------------------------------------------------------------
+// The same gradient without atomics, in a fixed order: the edges (r, j) are
+// sorted by their neighbour q (stable, so by r * k + j within one q), which
+// gives every point the list of rows that chose it; one thread per point
+// then sums its own terms (j ascending) and the terms of the rows that chose
+// it (in that list's order):
+//   dL/dp = sum_j 2 (p - p_{ids[p][j]}) g[p][j] + sum_{(r,j): ids[r][j] = p} 2 (p - p_r) g[r][j].
+// The result does not depend on scheduling: every run gives the same bits.
+// ---------------------------------------------------------------------------
+
+__global__ void k_edge_keys(const int32_t *__restrict__ ids, int64_t ne, int64_t stride,
+                            uint64_t *__restrict__ key, int32_t *__restrict__ edge) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const int32_t q = ids[e];
+  // an absent neighbour (-1) sorts after every point
+  key[e] = (q < 0 || q >= stride) ? (uint64_t)stride : (uint64_t)q;
+  edge[e] = (int32_t)e;
+}
+
+// first[p] = first sorted edge whose neighbour is >= p (a lower bound)
+__global__ void k_edge_starts(const uint64_t *__restrict__ key, int64_t ne, int64_t npts,
+                              int32_t *__restrict__ first) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > npts) return;
+  int64_t lo = 0, hi = ne;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (key[mid] < (uint64_t)p) lo = mid + 1;
+    else hi = mid;
+  }
+  first[p] = (int32_t)lo;
+}
+
+template <int D>
+__global__ void k_grad_gather(const double *__restrict__ xyz, int64_t stride, int64_t rows,
+                              int k, const int32_t *__restrict__ ids,
+                              const double *__restrict__ g, const int32_t *__restrict__ edge,
+                              const int32_t *__restrict__ first, double *__restrict__ grad) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= stride) return;
+  double pc[D], acc[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    pc[c] = xyz[c * stride + p];
+    acc[c] = 0.0;
+  }
+  if (p < rows) {
+    for (int j = 0; j < k; ++j) {
+      const int32_t q = ids[p * k + j];
+      if (q < 0 || q >= stride) continue;
+      const double w = g[p * k + j];
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc[c] += 2.0 * (pc[c] - xyz[c * stride + q]) * w;
+    }
+  }
+  const int32_t b = first[p], e = first[p + 1];
+  for (int32_t x = b; x < e; ++x) {
+    const int32_t ed = edge[x];
+    const int64_t r = ed / k;
+    const double w = g[ed];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] += 2.0 * (pc[c] - xyz[c * stride + r]) * w;
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) grad[c * stride + p] = acc[c];
+}
+
+hipError_t knn_backward_det(int dim, const double *xyz, int64_t stride, int64_t rows, int k,
+                            const int32_t *ids, const double *g, double *grad, hipStream_t s) {
+  if (stride <= 0) return hipSuccess;
+  const int64_t ne = rows * (int64_t)k;
+  if (ne == 0) return fill_f64(grad, 0.0, (int64_t)dim * stride, s);
+  uint64_t *key = nullptr, *ktmp = nullptr;
+  int32_t *edge = nullptr, *etmp = nullptr, *first = nullptr;
+  hipError_t e = dev_alloc_n(&key, ne, s);
+  if (e == hipSuccess) e = dev_alloc_n(&ktmp, ne, s);
+  if (e == hipSuccess) e = dev_alloc_n(&edge, ne, s);
+  if (e == hipSuccess) e = dev_alloc_n(&etmp, ne, s);
+  if (e == hipSuccess) e = dev_alloc_n(&first, stride + 1, s);
+  if (e == hipSuccess) {
+    k_edge_keys<<<(unsigned)((ne + 255) / 256), 256, 0, s>>>(ids, ne, stride, key, edge);
+    e = hipGetLastError();
+  }
+  int bits = 1;
+  while (bits < 63 && (uint64_t(1) << bits) <= (uint64_t)stride) ++bits;
+  if (e == hipSuccess) e = radix_sort_pairs(key, edge, ktmp, etmp, ne, bits, s);
+  if (e == hipSuccess) {
+    k_edge_starts<<<(unsigned)((stride + 1 + 255) / 256), 256, 0, s>>>(key, ne, stride, first);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    const unsigned grid = (unsigned)((stride + 255) / 256);
+    if (dim == 3)
+      k_grad_gather<3><<<grid, 256, 0, s>>>(xyz, stride, rows, k, ids, g, edge, first, grad);
+    else
+      k_grad_gather<2><<<grid, 256, 0, s>>>(xyz, stride, rows, k, ids, g, edge, first, grad);
+    e = hipGetLastError();
+  }
+  dev_release(key, s);
+  dev_release(ktmp, s);
+  dev_release(edge, s);
+  dev_release(etmp, s);
+  dev_release(first, s);
+  return e;
+}
+
+}  // namespace zd

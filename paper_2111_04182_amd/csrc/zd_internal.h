@@ -331,6 +331,9 @@ hipError_t fill_dead_rows(const int32_t *slot_of, int64_t cap, int k, int32_t *o
 // Backward
 hipError_t knn_backward(int dim, const double *xyz, int64_t stride, int64_t rows, int k,
                         const int32_t *ids, const double *g, double *grad, hipStream_t s);
+// the same without atomics, in a fixed order (bit-identical between runs)
+hipError_t knn_backward_det(int dim, const double *xyz, int64_t stride, int64_t rows, int k,
+                            const int32_t *ids, const double *g, double *grad, hipStream_t s);
 
 // Updates
 hipError_t count_outside_box(int dim, const double *xyz, int64_t m, const double *lo,

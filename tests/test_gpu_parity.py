@@ -248,25 +248,66 @@ def test_large_k_matches_oracle(k):
 
 # -------------------------------------------------------------- backward ----
 
-def test_backward_matches_closed_form_and_fd():
+@pytest.mark.parametrize("deterministic", [False, True])
+def test_backward_matches_closed_form_and_fd(deterministic):
     P = W.uniform(3000, 3, 400)
     g = zd.ZdTree(dev(P), 16, box=W.UNIT3)
     xyz = dev(P)
     ids, d2 = g.knn(8)
-    w = torch.from_numpy(np.random.default_rng(401).uniform(0.5, 2, (3000, 8))).cuda()
-    grad = zd.zd_knn_backward(xyz, ids, w).cpu().numpy().T
-    ref = oracle.knn_grad(P, ids.cpu().numpy(), w.cpu().numpy())
+    wn = np.random.default_rng(401).uniform(0.5, 2, (3000, 8))
+    w = torch.from_numpy(wn).cuda()
+    grad = zd.zd_knn_backward(xyz, ids, w, deterministic=deterministic).cpu().numpy().T
+    ref = oracle.knn_grad(P, ids.cpu().numpy(), wn)
     scale = np.abs(ref).max()
     assert np.abs(grad - ref).max() <= 1e-13 * max(scale, 1.0)
     assert np.abs(grad.sum(axis=0)).max() < 1e-10
+    # central finite differences of L = sum w * d2 over the fixed neighbour
+    # table: L is quadratic in each coordinate, so the difference is exact up
+    # to rounding (h_eff = fl(x + h) - fl(x - h))
+    nb = ids.cpu().numpy()
+    rows = np.repeat(np.arange(3000), 8)
+    cols = nb.ravel()
+    wf = wn.ravel()
+
+    def loss(Q):
+        diff = Q[rows] - Q[cols]
+        return float(np.sum(wf * np.sum(diff * diff, axis=1)))
+
+    rng = np.random.default_rng(402)
+    for i, c in zip(rng.integers(0, 3000, 25), rng.integers(0, 3, 25)):
+        Pp, Pm = P.copy(), P.copy()
+        Pp[i, c] += 1e-6
+        Pm[i, c] -= 1e-6
+        fd = (loss(Pp) - loss(Pm)) / (Pp[i, c] - Pm[i, c])
+        assert abs(fd - grad[i, c]) <= 1e-6 * max(abs(grad[i, c]), 1e-3), (i, c)
+    if deterministic:
+        again = zd.zd_knn_backward(xyz, ids, w, deterministic=True).cpu().numpy().T
+        assert np.array_equal(grad, again)
     g.close()
 
 
-def test_autograd_function():
+def test_backward_modes_after_deletes():
+    # dead rows (-1 neighbours) and rows beyond the table: both modes agree
+    # with the closed form
+    P = W.uniform(4000, 2, 403)
+    g = zd.ZdTree(dev(P), 8, box=W.UNIT2)
+    g.delete(torch.arange(0, 4000, 9, dtype=torch.int32, device="cuda"))
+    ids, d2 = g.knn(6)
+    wn = np.where(ids.cpu().numpy() >= 0, 1.0, 0.0)
+    w = torch.from_numpy(wn).cuda()
+    ref = oracle.knn_grad(P, ids.cpu().numpy(), wn)
+    for det in (False, True):
+        got = zd.zd_knn_backward(dev(P), ids, w, deterministic=det).cpu().numpy().T
+        assert np.abs(got - ref).max() <= 1e-13 * max(np.abs(ref).max(), 1.0), det
+    g.close()
+
+
+@pytest.mark.parametrize("deterministic", [False, True])
+def test_autograd_function(deterministic):
     P = W.uniform(2000, 3, 410)
     g = zd.ZdTree(dev(P), 16, box=W.UNIT3)
     xyz = dev(P).requires_grad_(True)
-    d2, ids = zd.ZdKnnSqDist.apply(xyz, g, 6)
+    d2, ids = zd.knn_sq_dist(xyz, g, 6, deterministic)
     loss = d2.sum()
     loss.backward()
     ref = oracle.knn_grad(P, ids.cpu().numpy(), np.ones((2000, 6)))
