@@ -645,7 +645,7 @@ zd_status zd_insert_batch(zd_tree t, const double *xyz, int64_t m, int32_t *out_
   if (!t || m < 0) return ZD_EINVAL;
   if (t->broken) return ZD_EDEVICE;
   if (m == 0) return ZD_OK;
-  if (!xyz || t->cap + m > kMaxIds || t->st.n + m > kMaxLive) return ZD_EINVAL;
+  if (!xyz || t->cap + m > kMaxIds || t->live + m > kMaxLive) return ZD_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   const int dim = t->dim;
   hipError_t e = bind_stream(t, s);
