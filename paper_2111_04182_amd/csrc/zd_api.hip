@@ -189,7 +189,8 @@ void pending_release(zd_tree t) {
 // Relink the tree over the points of t->st (keys sorted, coordinates and
 // slot map in place).  A forest passes the cloud of every position and the
 // leaf size of every cloud.
-hipError_t relink(zd_tree t, const int32_t *seg = nullptr, const int32_t *seg_leaf = nullptr) {
+hipError_t relink(zd_tree t, const int32_t *seg = nullptr, const int32_t *seg_leaf = nullptr,
+                  int32_t max_leaf = 0) {
   // leaves and nodes are renumbered: the per-leaf state of in-place small
   // batches goes (every caller has folded their points in, or has none)
   pending_release(t);
@@ -200,6 +201,7 @@ hipError_t relink(zd_tree t, const int32_t *seg = nullptr, const int32_t *seg_le
   BuildBuffers b = t->buffers(flag);
   b.seg = seg;
   b.seg_leaf = seg_leaf;
+  b.max_leaf = max_leaf;
   e = build_tree_links(t->dim, t->L, t->st.n, b, s);
   dev_release(flag, s);
   return e;
@@ -1094,6 +1096,7 @@ struct zd_forest_s {
   double *seg_lo = nullptr;     // device [C][3]
   double *seg_S = nullptr;      // device [C][3]
   int32_t *seg_leaf = nullptr;  // device [C] or null (one leaf size)
+  int32_t max_leaf = 0;         // the largest leaf size of any cloud
   int4 *tiles = nullptr;        // sort tiles, none spanning two clouds
   int ntiles = 0;
   int4 *groups = nullptr;       // query groups (first, last, cloud first, cloud last)
@@ -1162,6 +1165,9 @@ zd_status forest_setup(const zd_params *p, const double *xyz, int64_t n, const i
   f->t = t;
   f->C = C;
   f->xyz = xyz;
+  f->max_leaf = p->leaf_size;
+  if (leaf_sizes)
+    for (int32_t c = 0; c < C; ++c) f->max_leaf = std::max(f->max_leaf, leaf_sizes[c]);
   t->stream = s;
   t->dim = dim;
   t->L = p->leaf_size;
@@ -1249,7 +1255,7 @@ hipError_t forest_build_pass(zd_forest f, hipStream_t s) {
   dev_release(itmp, s);
   if (e == hipSuccess)
     e = gather_points(t->dim, f->xyz, n, t->st.id, n, t->st.X, t->st.Y, t->st.Z, t->slot_of, s);
-  if (e == hipSuccess) e = relink(t, f->seg, f->seg_leaf);
+  if (e == hipSuccess) e = relink(t, f->seg, f->seg_leaf, f->max_leaf);
   return e;
 }
 

@@ -235,29 +235,55 @@ __global__ void k_split_bits(const uint64_t *__restrict__ key, const int32_t *__
 // point i iff no split between them exceeds b, so the run extends from i
 // while the adjacent split bits stay <= b, and the scan stops once more than
 // L points are seen.
+__device__ __forceinline__ int32_t leaf_test(int b, int Li, const int8_t *sb, int64_t i,
+                                             int64_t lo, int64_t hi) {
+  if (b >= 64) return 1;  // cloud boundaries are always internal: no leaf mixes clouds
+  if (b < 0) return 0;
+  int64_t left = 1, right = 1;
+  for (int64_t y = i - 1; y >= lo && left + right <= Li; --y) {
+    if (sb[y] > b) break;
+    ++left;
+  }
+  for (int64_t y = i + 1; y < hi && left + right <= Li; ++y) {
+    if (sb[y] > b) break;
+    ++right;
+  }
+  return left + right > Li ? 1 : 0;
+}
+
+// Leaf sizes up to kFlagHalo: the workgroup's 256 split bits and kFlagHalo
+// on each side are staged in LDS, and the scans read LDS.  Positions outside
+// the array read as a split above every bit, which ends a scan where the
+// array ends.
+constexpr int kFlagBlock = 256;
+constexpr int kFlagHalo = 256;
+
+__global__ void __launch_bounds__(kFlagBlock)
+    k_split_flags_lds(const int8_t *__restrict__ sb, const int32_t *__restrict__ seg, int64_t n,
+                      int L, int H, const int32_t *__restrict__ seg_leaf,
+                      int32_t *__restrict__ flag) {
+  __shared__ int8_t s[kFlagBlock + 2 * kFlagHalo];
+  const int64_t i0 = (int64_t)blockIdx.x * kFlagBlock;
+  for (int q = threadIdx.x; q < kFlagBlock + 2 * H; q += kFlagBlock) {
+    const int64_t y = i0 - H + q;
+    s[q] = (y >= 0 && y < n - 1) ? sb[y] : (int8_t)127;
+  }
+  __syncthreads();
+  const int64_t i = i0 + threadIdx.x;
+  if (i >= n - 1) return;
+  const int c = H + (int)threadIdx.x;
+  const int Li = seg_leaf ? seg_leaf[seg[i]] : L;  // <= H
+  flag[i] = leaf_test(s[c], Li, s, c, 0, kFlagBlock + 2 * H);
+}
+
+// Any leaf size: the scans read device memory.
 __global__ void k_split_flags(const int8_t *__restrict__ sb, const int32_t *__restrict__ seg,
                               int64_t n, int L, const int32_t *__restrict__ seg_leaf,
                               int32_t *__restrict__ flag) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n - 1) return;
-  const int b = sb[i];
-  int32_t f = 0;
-  if (b >= 64) {
-    f = 1;  // cloud boundaries are always internal: no leaf mixes clouds
-  } else if (b >= 0) {
-    const int Li = seg_leaf ? seg_leaf[seg[i]] : L;
-    int64_t left = 1, right = 1;
-    for (int64_t y = i - 1; y >= 0 && left + right <= Li; --y) {
-      if (sb[y] > b) break;
-      ++left;
-    }
-    for (int64_t y = i + 1; y < n - 1 && left + right <= Li; ++y) {
-      if (sb[y] > b) break;
-      ++right;
-    }
-    f = (left + right > Li) ? 1 : 0;
-  }
-  flag[i] = f;
+  const int Li = seg_leaf ? seg_leaf[seg[i]] : L;
+  flag[i] = leaf_test(sb[i], Li, sb, i, 0, n - 1);
 }
 
 // ---------------------------------------------------------------- compact --
@@ -501,7 +527,12 @@ hipError_t build_tree_links(int dim, int leaf_size, int64_t n, const BuildBuffer
       e = hipGetLastError();
     }
     if (e == hipSuccess) {
-      k_split_flags<<<grid_n, 256, 0, s>>>(sb, b.seg, n, leaf_size, b.seg_leaf, b.flag);
+      const int H = b.max_leaf > 0 ? b.max_leaf : leaf_size;  // largest leaf size in use
+      if (H <= kFlagHalo)
+        k_split_flags_lds<<<grid_n, kFlagBlock, 0, s>>>(sb, b.seg, n, leaf_size, H, b.seg_leaf,
+                                                        b.flag);
+      else
+        k_split_flags<<<grid_n, 256, 0, s>>>(sb, b.seg, n, leaf_size, b.seg_leaf, b.flag);
       e = hipGetLastError();
     }
     // exclusive split counts: the node number of each split for the

@@ -279,6 +279,7 @@ struct BuildBuffers {
   int32_t *flag;     // scratch [n]
   const int32_t *seg = nullptr;       // forest: cloud of each sorted position
   const int32_t *seg_leaf = nullptr;  // forest: leaf size of each cloud
+  int32_t max_leaf = 0;               // forest: the largest entry of seg_leaf
 };
 // aos (nullable): also write each point as one (x, y, z, 0) / (x, y) record,
 // so that the later gather reads one aligned record per point instead of
