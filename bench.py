@@ -564,7 +564,8 @@ def leg_skewed(leaf, steps, n=10_000_000, k=10, verify=50):
 def leg_forest(steps, k=16):
     """4096 Gaussian-mixture clouds: the tuner (3 timings per candidate),
     then build + all-points k=16 of every cloud as one captured-graph
-    replay, against one zd_build + zd_knn pair per cloud on the same GPU."""
+    replay, the same as one persistent kernel launch, and one zd_build +
+    zd_knn pair per cloud on the same GPU."""
     import torch
     import paper_2111_04182_amd as zd
     import workloads as W
@@ -580,6 +581,15 @@ def leg_forest(steps, k=16):
     torch.cuda.synchronize()
     ms_forest, _ = _events(plan.run, max(5, steps))
     plan.check()
+    # the same build + query as one persistent kernel launch (same leaf sizes)
+    log("bench forest: persistent launch")
+    pplan = zd.ZdForestPlan(xyz, off, k, leaf_sizes=ls, persistent=True)
+    pplan.run()
+    torch.cuda.synchronize()
+    ms_persistent, _ = _events(pplan.run, max(5, steps))
+    pplan.check()
+    persistent_same = bool(torch.equal(pplan.ids, plan.ids) and torch.equal(pplan.d2, plan.d2))
+    pplan.close()
     # the same work as one zd_build + zd_knn pair per cloud (boxes precomputed
     # on the host so no call synchronises)
     clouds = []
@@ -611,6 +621,8 @@ def leg_forest(steps, k=16):
     return {"N": N, "clouds": len(off) - 1, "k": k, "forest_graph_ms": ms_forest,
             "queries_per_s": N / ms_forest * 1e3, "per_cloud_calls_ms": ms_pc,
             "speedup_vs_per_cloud": ms_pc / ms_forest, "rows_match_per_cloud": ok,
+            "persistent_launch_ms": ms_persistent,
+            "persistent_rows_match_graph": persistent_same,
             "leaf_size_by_bucket": rep.get("choice"), "query_waves": waves,
             "autotune_best_ms": rep.get("best_ms"), "autotune_reps": 3}
 

@@ -313,6 +313,24 @@ ZD_API zd_status zd_forest_plan(const zd_params *params, const double *xyz, int6
                                 double *out_d2, void *stream, zd_forest *out);
 ZD_API zd_status zd_forest_run(zd_forest forest, void *stream);
 
+/* zd_forest_plan with the whole build + query as ONE persistent kernel
+ * launch (after two fill kernels that clear its counters), captured in the
+ * plan's graph and replayed by zd_forest_run.  Inside the launch, each
+ * workgroup takes clouds largest first and builds each one alone with
+ * workgroup barriers only (its keys, sort, leaf test, node numbering, boxes
+ * and links, numbered inside the cloud's own range of the shared arrays);
+ * then every wavefront takes 64-point query groups, in the same cloud
+ * order, waiting for its group's cloud to be built.  Rows, trees and
+ * errors are those of zd_forest_plan; zd_forest_knn and zd_forest_check
+ * work on the trees of the last run.  A wait inside the launch that runs
+ * out (10 s) skips its group and makes zd_forest_check report ZD_EDEVICE.
+ * Scratch: about 13 bytes per point, and the plan's tables. */
+ZD_API zd_status zd_forest_plan_persistent(const zd_params *params, const double *xyz,
+                                           int64_t n, const int64_t *offsets, int32_t n_clouds,
+                                           const int32_t *leaf_sizes, int32_t k,
+                                           int32_t *out_ids, double *out_d2, void *stream,
+                                           zd_forest *out);
+
 /* Synchronise the forest's stream and run the self-checks of its build and
  * searches (as zd_check).  Errors: ZD_EINVAL (NULL), ZD_EDEVICE. */
 ZD_API zd_status zd_forest_check(zd_forest forest);

@@ -22,6 +22,7 @@ ZD_KMAX = 100
 
 EXPORTED = ("zd_build", "zd_knn", "zd_knn_root", "zd_knn_noalloc", "zd_insert_batch", "zd_delete_batch", "zd_free", "zd_info",
             "zd_check", "zd_pending", "zd_set_walk_limit", "zd_export", "zd_knn_backward", "zd_knn_backward_det", "zd_forest_build", "zd_forest_knn", "zd_forest_plan",
+            "zd_forest_plan_persistent",
             "zd_forest_run", "zd_forest_check", "zd_forest_free", "zd_status_str")
 
 
@@ -87,6 +88,8 @@ def lib() -> C.CDLL:
         L.zd_forest_plan.restype = C.c_int
         L.zd_forest_plan.argtypes = [C.POINTER(_Params), vp, i64, vp, i32, vp, i32, vp, vp, vp,
                                      C.POINTER(vp)]
+        L.zd_forest_plan_persistent.restype = C.c_int
+        L.zd_forest_plan_persistent.argtypes = L.zd_forest_plan.argtypes
         L.zd_forest_run.restype = C.c_int
         L.zd_forest_run.argtypes = [vp, vp]
         L.zd_forest_check.restype = C.c_int
@@ -365,6 +368,18 @@ def zd_forest_plan(xyz, offsets, k, out_ids, out_d2, leaf_size=16, leaf_sizes=No
     return out
 
 
+def zd_forest_plan_persistent(xyz, offsets, k, out_ids, out_d2, leaf_size=16, leaf_sizes=None,
+                              box=None, shift_seed=0, shift=None, stream=None):
+    p, dim, n, off, ls, keep = _forest_args(xyz, offsets, leaf_size, leaf_sizes, box,
+                                            shift_seed, shift, 0)
+    out = C.c_void_p()
+    _check(lib().zd_forest_plan_persistent(C.byref(p), _dptr(xyz), n, _hptr(off), len(off) - 1,
+                                           _hptr(ls), k, _dptr(out_ids), _dptr(out_d2),
+                                           _stream(stream), C.byref(out)),
+           "zd_forest_plan_persistent")
+    return out
+
+
 def zd_forest_run(forest, stream=None):
     _check(lib().zd_forest_run(forest, _stream(stream)), "zd_forest_run")
 
@@ -412,16 +427,22 @@ class ZdForest:
 
 class ZdForestPlan:
     """Build + all-points query of a forest captured as one HIP graph; run()
-    replays it on the current contents of xyz, filling self.ids / self.d2."""
+    replays it on the current contents of xyz, filling self.ids / self.d2.
+    persistent=True captures the single persistent launch
+    (zd_forest_plan_persistent) instead of the pass-by-pass sequence."""
 
     def __init__(self, xyz, offsets, k, leaf_size=16, leaf_sizes=None, box=None, shift_seed=0,
-                 shift=None, stream=None, query_waves=0):
+                 shift=None, stream=None, query_waves=0, persistent=False):
         n = xyz.shape[1]
         self._xyz = xyz
         self.ids = torch.empty((n, k), dtype=torch.int32, device="cuda")
         self.d2 = torch.empty((n, k), dtype=torch.float64, device="cuda")
-        self._h = zd_forest_plan(xyz, offsets, k, self.ids, self.d2, leaf_size, leaf_sizes, box,
-                                 shift_seed, shift, stream, query_waves)
+        if persistent:
+            self._h = zd_forest_plan_persistent(xyz, offsets, k, self.ids, self.d2, leaf_size,
+                                                leaf_sizes, box, shift_seed, shift, stream)
+        else:
+            self._h = zd_forest_plan(xyz, offsets, k, self.ids, self.d2, leaf_size, leaf_sizes,
+                                     box, shift_seed, shift, stream, query_waves)
 
     def run(self, stream=None):
         zd_forest_run(self._h, stream)

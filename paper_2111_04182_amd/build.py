@@ -18,7 +18,7 @@ OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libzd.so")
 
 SOURCES = ["zd_knn_all_d3.hip", "zd_knn_all_d2.hip", "zd_knn_ext_d3.hip", "zd_knn_ext_d2.hip",
-           "zd_knn_root_d3.hip", "zd_knn_root_d2.hip",
+           "zd_knn_root_d3.hip", "zd_knn_root_d2.hip", "zd_persist_d3.hip", "zd_persist_d2.hip",
            "zd_scan.hip", "zd_sort.hip", "zd_build.hip", "zd_knn.hip", "zd_update.hip",
            "zd_grad.hip", "zd_api.hip"]
 

@@ -1101,6 +1101,17 @@ struct zd_forest_s {
   int ntiles = 0;
   int4 *groups = nullptr;       // query groups (first, last, cloud first, cloud last)
   int64_t ngroups = 0;
+  // one persistent launch (zd_forest_plan_persistent): clouds in build
+  // order, query groups in that order, ready flags, counters, scratch
+  bool persistent = false;
+  int32_t *p_order = nullptr;
+  int4 *p_groups = nullptr;
+  int64_t p_ngroups = 0;
+  int32_t *p_ready = nullptr;
+  int32_t *p_ctl = nullptr;
+  uint64_t *p_key2 = nullptr;
+  int32_t *p_id2 = nullptr;
+  int8_t *p_sb = nullptr;
   // captured build + query
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -1125,6 +1136,13 @@ void forest_destroy(zd_forest f) {
   dev_release(f->seg_leaf, s);
   dev_release(f->tiles, s);
   dev_release(f->groups, s);
+  dev_release(f->p_order, s);
+  dev_release(f->p_groups, s);
+  dev_release(f->p_ready, s);
+  dev_release(f->p_ctl, s);
+  dev_release(f->p_key2, s);
+  dev_release(f->p_id2, s);
+  dev_release(f->p_sb, s);
   destroy(f->t);
   delete f;
 }
@@ -1322,6 +1340,102 @@ zd_status zd_forest_plan(const zd_params *params, const double *xyz, int64_t n,
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&f->exec, f->graph, nullptr, nullptr, 0);
   f->t->stream = s;
+  if (e != hipSuccess) {
+    forest_destroy(f);
+    return to_status(e);
+  }
+  *out = f;
+  return ZD_OK;
+}
+
+// The wall-clock ticks of `seconds` on the current device.
+static int64_t wall_ticks(int seconds) {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    khz = 100000;
+  return (int64_t)khz * 1000 * seconds;
+}
+
+zd_status zd_forest_plan_persistent(const zd_params *params, const double *xyz, int64_t n,
+                                    const int64_t *offsets, int32_t n_clouds,
+                                    const int32_t *leaf_sizes, int32_t k, int32_t *out_ids,
+                                    double *out_d2, void *stream, zd_forest *out) {
+  if (k < 1) return ZD_EINVAL;
+  if (k > ZD_KMAX) return ZD_EKMAX;
+  if (n > 0 && (!out_ids || !out_d2)) return ZD_EINVAL;
+  zd_forest f = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  zd_status st = forest_setup(params, xyz, n, offsets, n_clouds, leaf_sizes, s, &f);
+  if (st != ZD_OK) return st;
+  zd_tree t = f->t;
+  const int32_t C = n_clouds;
+  f->persistent = true;
+  // clouds by decreasing size, and their 64-point query groups in that order
+  std::vector<int32_t> order(C);
+  for (int32_t c = 0; c < C; ++c) order[c] = c;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
+  });
+  std::vector<int4> qg;
+  for (int32_t c : order)
+    for (int64_t g = offsets[c]; g < offsets[c + 1]; g += 64)
+      qg.push_back(make_int4((int)g, (int)std::min<int64_t>(g + 63, offsets[c + 1] - 1), c, 0));
+  f->p_ngroups = (int64_t)qg.size();
+  hipError_t e = dev_alloc_n(&f->p_order, C, s);
+  if (e == hipSuccess) e = dev_alloc_n(&f->p_groups, f->p_ngroups, s);
+  if (e == hipSuccess) e = dev_alloc_n(&f->p_ready, C, s);
+  if (e == hipSuccess) e = dev_alloc_n(&f->p_ctl, 2, s);
+  if (e == hipSuccess) e = dev_alloc_n(&f->p_key2, n, s);
+  if (e == hipSuccess) e = dev_alloc_n(&f->p_id2, n, s);
+  if (e == hipSuccess) e = dev_alloc_n(&f->p_sb, n, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess)
+    e = hipMemcpy(f->p_order, order.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !qg.empty())
+    e = hipMemcpy(f->p_groups, qg.data(), sizeof(int4) * qg.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&f->cap, hipStreamNonBlocking);
+  PersistArgs a{};
+  a.xyz = xyz;
+  a.n = n;
+  a.offsets = f->offsets;
+  a.order = f->p_order;
+  a.C = C;
+  a.leaf_size = f->seg_leaf;
+  a.L = t->L;
+  a.g = t->geo;
+  a.have_box = f->have_box ? 1 : 0;
+  for (int c = 0; c < 3; ++c) {
+    a.box.lo[c] = f->box_lo[c];
+    a.box.hi[c] = f->box_hi[c];
+  }
+  a.key2 = f->p_key2;
+  a.id2 = f->p_id2;
+  a.sb = f->p_sb;
+  a.slot_of = t->slot_of;
+  a.ctl = f->p_ctl;
+  a.ready = f->p_ready;
+  a.qgroups = f->p_groups;
+  a.ngroups = f->p_ngroups;
+  a.out_ids = out_ids;
+  a.out_d2 = out_d2;
+  a.k = k;
+  a.wait_ticks = wall_ticks(10);
+  const PersistTree pt{t->st.key, t->st.id, t->st.X, t->st.Y, t->st.Z, t->st.leaf_of,
+                       t->st.leaf_begin, t->st.leaf_parent, t->st.inode, t->meta};
+  // the graph: clear the counters and flags (fill kernels), then the launch
+  if (e == hipSuccess) e = hipStreamBeginCapture(f->cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t e1 = fill_i32(f->p_ctl, 0, 2, f->cap);
+    if (e1 == hipSuccess) e1 = fill_i32(f->p_ready, 0, C, f->cap);
+    if (e1 == hipSuccess && n > 0)
+      e1 = t->dim == 3 ? forest_persistent_d3(a, pt, t->view(), f->cap)
+                       : forest_persistent_d2(a, pt, t->view(), f->cap);
+    hipError_t e2 = hipStreamEndCapture(f->cap, &f->graph);
+    e = e1 != hipSuccess ? e1 : e2;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&f->exec, f->graph, nullptr, nullptr, 0);
+  t->stream = s;
   if (e != hipSuccess) {
     forest_destroy(f);
     return to_status(e);

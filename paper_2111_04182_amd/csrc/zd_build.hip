@@ -229,28 +229,6 @@ __global__ void k_split_bits(const uint64_t *__restrict__ key, const int32_t *__
   sb[i] = (int8_t)pos_split_bit(key, seg, i);
 }
 
-// Position i (between sorted points i and i+1) is an internal node iff the
-// run of points that share the prefix above its split bit b holds more than
-// L points (the leaf test of Algorithm 1).  Point x shares that prefix with
-// point i iff no split between them exceeds b, so the run extends from i
-// while the adjacent split bits stay <= b, and the scan stops once more than
-// L points are seen.
-__device__ __forceinline__ int32_t leaf_test(int b, int Li, const int8_t *sb, int64_t i,
-                                             int64_t lo, int64_t hi) {
-  if (b >= 64) return 1;  // cloud boundaries are always internal: no leaf mixes clouds
-  if (b < 0) return 0;
-  int64_t left = 1, right = 1;
-  for (int64_t y = i - 1; y >= lo && left + right <= Li; --y) {
-    if (sb[y] > b) break;
-    ++left;
-  }
-  for (int64_t y = i + 1; y < hi && left + right <= Li; ++y) {
-    if (sb[y] > b) break;
-    ++right;
-  }
-  return left + right > Li ? 1 : 0;
-}
-
 // Leaf sizes up to kFlagHalo: the workgroup's 256 split bits and kFlagHalo
 // on each side are staged in LDS, and the scans read LDS.  Positions outside
 // the array read as a split above every bit, which ends a scan where the
@@ -300,19 +278,6 @@ __global__ void k_compact(const int32_t *__restrict__ flag, const int32_t *__res
 }
 
 // ------------------------------------------------- leaves + bottom-up links --
-
-// Values a child hands to its parent during the climb travel through device-
-// scope atomics only (64-bit exchanges to publish, no-op RMWs to read), which
-// are coherent across the chip's L2 slices; a __threadfence() here would write
-// back and invalidate the whole L2 at every step.
-__device__ __forceinline__ void publish_f64(double *p, double v) {
-  atomicExch(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
-}
-__device__ __forceinline__ double fetch_f64(double *p) {
-  return __longlong_as_double((long long)atomicOr(reinterpret_cast<unsigned long long *>(p), 0ULL));
-}
-__device__ __forceinline__ void publish_i32(int32_t *p, int32_t v) { atomicExch(p, v); }
-__device__ __forceinline__ int32_t fetch_i32(int32_t *p) { return atomicOr(p, 0); }
 
 constexpr int kLeafBlock = 256;
 

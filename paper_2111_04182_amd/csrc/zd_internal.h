@@ -122,6 +122,41 @@ __device__ __forceinline__ int split_bit(uint64_t a, uint64_t b) {
   return x ? high_bit64(x) : -1;
 }
 
+// Position i (between sorted points i and i+1) is an internal node iff the
+// run of points that share the prefix above its split bit b holds more than
+// L points (the leaf test of Algorithm 1).  Point x shares that prefix with
+// point i iff no split between them exceeds b, so the run extends from i
+// while the adjacent split bits stay <= b, and the scan stops once more than
+// L points are seen.
+__device__ __forceinline__ int32_t leaf_test(int b, int Li, const int8_t *sb, int64_t i,
+                                             int64_t lo, int64_t hi) {
+  if (b >= 64) return 1;  // cloud boundaries are always internal: no leaf mixes clouds
+  if (b < 0) return 0;
+  int64_t left = 1, right = 1;
+  for (int64_t y = i - 1; y >= lo && left + right <= Li; --y) {
+    if (sb[y] > b) break;
+    ++left;
+  }
+  for (int64_t y = i + 1; y < hi && left + right <= Li; ++y) {
+    if (sb[y] > b) break;
+    ++right;
+  }
+  return left + right > Li ? 1 : 0;
+}
+
+// Values a child hands to its parent during the climb travel through device-
+// scope atomics only (64-bit exchanges to publish, no-op RMWs to read), which
+// are coherent across the chip's L2 slices; a __threadfence() here would write
+// back and invalidate the whole L2 at every step.
+__device__ __forceinline__ void publish_f64(double *p, double v) {
+  atomicExch(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
+}
+__device__ __forceinline__ double fetch_f64(double *p) {
+  return __longlong_as_double((long long)atomicOr(reinterpret_cast<unsigned long long *>(p), 0ULL));
+}
+__device__ __forceinline__ void publish_i32(int32_t *p, int32_t v) { atomicExch(p, v); }
+__device__ __forceinline__ int32_t fetch_i32(int32_t *p) { return atomicOr(p, 0); }
+
 // One coordinate to its integer cell: u = (x - lo) * S, floor, clamp into
 // [0, 2^(B-1) - 1]; monotone non-decreasing in x (NaN goes to cell 0).
 __device__ __forceinline__ uint64_t cell_of(double x, double lo, double S, int B) {
@@ -309,6 +344,47 @@ hipError_t tree_depth(const int32_t *leaf_parent, const INode *inode, int64_t n_
 // [64w, 64w + 64); otherwise wavefront w answers [groups[w].x, groups[w].y],
 // which lie in the cloud [groups[w].z, groups[w].w] (a forest's groups never
 // span two clouds).  query_waves: wavefronts per workgroup (1, 2 or 4).
+// The persistent forest launch (zd_persist_impl.h): the forest's arrays,
+// which its builds write and its queries read through a TreeView.
+struct PersistTree {
+  uint64_t *key;
+  int32_t *id;
+  double *X, *Y, *Z;
+  int32_t *leaf_of, *leaf_begin, *leaf_parent;
+  INode *inode;
+  int32_t *meta;
+};
+
+struct PersistArgs {
+  const double *xyz;        // the caller's points, SoA [dim][n]
+  int64_t n;
+  const int64_t *offsets;   // [C + 1]
+  const int32_t *order;     // [C] clouds by decreasing size
+  int32_t C;
+  const int32_t *leaf_size; // [C], or null: L for every cloud
+  int32_t L;
+  Geometry g;               // dim, B and shift (lo and S are per cloud)
+  int32_t have_box;         // one declared box for every cloud
+  Box3 box;
+  uint64_t *key2;           // [n] sort scratch
+  int32_t *id2;             // [n] sort scratch
+  int8_t *sb;               // [n] split bits
+  int32_t *slot_of;         // [n]
+  int32_t *ctl;             // [0]: next cloud to build, [1]: next query group
+  int32_t *ready;           // [C]: builder wavefronts done (zero before the launch)
+  const int4 *qgroups;      // {first, last, cloud, 0}, clouds in build order
+  int64_t ngroups;
+  int32_t *out_ids;
+  double *out_d2;
+  int32_t k;
+  int64_t wait_ticks;       // bound on one wait, in wall-clock ticks
+};
+
+hipError_t forest_persistent_d2(const PersistArgs &a, const PersistTree &pt, const TreeView &t,
+                                hipStream_t s);
+hipError_t forest_persistent_d3(const PersistArgs &a, const PersistTree &pt, const TreeView &t,
+                                hipStream_t s);
+
 hipError_t knn_all_points(int dim, const TreeView &t, int k, int32_t *out_ids, double *out_d2,
                           hipStream_t s, int query_waves, const int4 *groups = nullptr,
                           int64_t ngroups = 0);

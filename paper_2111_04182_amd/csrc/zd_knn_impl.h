@@ -848,29 +848,17 @@ constexpr int knn_all_min_waves() {
   return K == 10 ? 6 : (K == 12 ? 5 : (K == 20 || K == 24 || K == 32 ? 3 : 1));
 }
 
+// One wavefront answers the all-points rows of sorted positions [g0, last]
+// (at most 64), which lie in the cloud [c_lo, c_hi] (the whole tree for a
+// single tree).  `smem` is the workgroup's dynamic LDS, w the wavefront's
+// index in the workgroup.
 template <int D, int K, bool kPool>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(knn_all_min_waves<K>())))
-k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
-                                                 double *__restrict__ out_d2,
-                                                 const int4 *__restrict__ groups, int64_t ngroups) {
-  extern __shared__ __align__(16) char smem[];
+__device__ __forceinline__ void all_points_group(const TreeView &t, int k,
+                                                 int32_t *__restrict__ out_ids,
+                                                 double *__restrict__ out_d2, int64_t g0,
+                                                 int64_t last, int64_t c_lo, int64_t c_hi,
+                                                 char *smem, int w) {
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int64_t gw = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + w;
-  int64_t g0, last, c_lo, c_hi;  // the group, and the cloud that holds it
-  if (groups) {
-    if (gw >= ngroups) return;
-    g0 = uni(groups[gw].x);
-    last = uni(groups[gw].y);
-    c_lo = uni(groups[gw].z);
-    c_hi = uni(groups[gw].w);
-  } else {
-    g0 = gw * 64;
-    if (g0 >= t.n) return;
-    last = min(g0 + 63, t.n - 1);
-    c_lo = 0;
-    c_hi = t.n - 1;
-  }
   const int64_t i = min(g0 + lane, last);
   WaveSearch<D, K, false, kPool> s(t, nullptr);
   bind_lds(s, smem, w);
@@ -908,6 +896,31 @@ k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
   s.run_from(G);
   s.report();
   if (s.valid) s.h.write(k, out_ids + (int64_t)s.self * k, out_d2 + (int64_t)s.self * k);
+}
+
+template <int D, int K, bool kPool>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(knn_all_min_waves<K>())))
+k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
+                                                 double *__restrict__ out_d2,
+                                                 const int4 *__restrict__ groups, int64_t ngroups) {
+  extern __shared__ __align__(16) char smem[];
+  const int w = threadIdx.x >> 6;
+  const int64_t gw = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + w;
+  int64_t g0, last, c_lo, c_hi;  // the group, and the cloud that holds it
+  if (groups) {
+    if (gw >= ngroups) return;
+    g0 = uni(groups[gw].x);
+    last = uni(groups[gw].y);
+    c_lo = uni(groups[gw].z);
+    c_hi = uni(groups[gw].w);
+  } else {
+    g0 = gw * 64;
+    if (g0 >= t.n) return;
+    last = min(g0 + 63, t.n - 1);
+    c_lo = 0;
+    c_hi = t.n - 1;
+  }
+  all_points_group<D, K, kPool>(t, k, out_ids, out_d2, g0, last, c_lo, c_hi, smem, w);
 }
 
 // External rows: wavefront w answers the Morton-sorted queries

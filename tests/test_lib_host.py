@@ -68,6 +68,9 @@ def test_argument_errors_need_no_device(L):
     assert L.zd_set_walk_limit(None, 0) == B.ZD_EINVAL
     assert L.zd_free(None) == B.ZD_OK
     assert L.zd_knn_backward(4, None, 0, 0, 1, None, None, None, None) == B.ZD_EINVAL
+    for k, want in ((0, B.ZD_EINVAL), (B.ZD_KMAX + 1, B.ZD_EKMAX), (4, B.ZD_EINVAL)):
+        assert L.zd_forest_plan_persistent(None, None, 0, None, 0, None, k, None, None, None,
+                                           C.byref(out)) == want
     assert L.zd_knn_backward(3, None, 10, 20, 1, None, None, None, None) == B.ZD_EINVAL
     assert out.value is None
 
