@@ -7,6 +7,7 @@
 #include <new>
 #include <algorithm>
 #include <mutex>
+#include <queue>
 #include <vector>
 
 using namespace zd;
@@ -1371,14 +1372,36 @@ zd_status zd_forest_plan_persistent(const zd_params *params, const double *xyz, 
   zd_tree t = f->t;
   const int32_t C = n_clouds;
   f->persistent = true;
-  // clouds by decreasing size, and their 64-point query groups in that order
+  // Builds take clouds by decreasing size.  Query groups go in the order
+  // the clouds are predicted to be built: a list schedule of the builds on
+  // the launch's workgroups (about four per CU), each cloud costing its
+  // size plus a fixed overhead, so that wavefronts rarely wait for a build.
   std::vector<int32_t> order(C);
   for (int32_t c = 0; c < C; ++c) order[c] = c;
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
     return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
   });
+  int cus = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  std::vector<double> done(C);
+  {
+    std::priority_queue<double, std::vector<double>, std::greater<double>> slots;
+    for (int i = 0; i < 4 * cus; ++i) slots.push(0.0);
+    for (int32_t c : order) {
+      const double t0 = slots.top();
+      slots.pop();
+      done[c] = t0 + 4096.0 + (double)(offsets[c + 1] - offsets[c]);
+      slots.push(done[c]);
+    }
+  }
+  std::vector<int32_t> qorder(order);
+  std::stable_sort(qorder.begin(), qorder.end(),
+                   [&](int32_t a, int32_t b) { return done[a] < done[b]; });
   std::vector<int4> qg;
-  for (int32_t c : order)
+  for (int32_t c : qorder)
     for (int64_t g = offsets[c]; g < offsets[c + 1]; g += 64)
       qg.push_back(make_int4((int)g, (int)std::min<int64_t>(g + 63, offsets[c + 1] - 1), c, 0));
   f->p_ngroups = (int64_t)qg.size();

@@ -372,7 +372,7 @@ struct PersistArgs {
   int32_t *slot_of;         // [n]
   int32_t *ctl;             // [0]: next cloud to build, [1]: next query group
   int32_t *ready;           // [C]: builder wavefronts done (zero before the launch)
-  const int4 *qgroups;      // {first, last, cloud, 0}, clouds in build order
+  const int4 *qgroups;      // {first, last, cloud, 0}, by predicted build completion
   int64_t ngroups;
   int32_t *out_ids;
   double *out_d2;

@@ -17,7 +17,8 @@
 //    builder releases its stores and then counts itself into the cloud's
 //    ready word.
 //  * queries: once the cloud counter runs out, every wavefront takes 64-point
-//    query groups, in the clouds' build order, from a second counter, waits
+//    query groups, in the order the host predicts the clouds to be built,
+//    from a second counter, waits
 //    for the group's cloud to be ready (every builder wavefront counted; an
 //    acquire fence the first time it meets that cloud) and answers the
 //    group like the all-points kernel.
@@ -36,10 +37,12 @@ constexpr int kPWaves = 4;
 constexpr int kPThreads = 64 * kPWaves;  // one radix digit per thread
 constexpr int kPItems = 8;
 constexpr int kPChunk = kPThreads * kPItems;  // keys ranked per sort step
+constexpr int kPHalo = 256;                   // leaf sizes the leaf test serves from LDS
 
 struct PBuildLds {
   int32_t hist[256];              // digit counts, then running output bases
   int32_t wc[kPWaves][256];       // per-wave digit counters of a sort step
+  int8_t sbw[kPThreads + 2 * kPHalo];  // split bits of a leaf-test step
   int32_t wsum[kPWaves];
   double box[kPWaves][6];         // per-wave bounding box
   double geo[6];                  // the cloud's lo[3], S[3]
@@ -78,8 +81,8 @@ __device__ __forceinline__ uint32_t p_digit(uint64_t k, int shift) {
 // gives each digit's first output position; the range is then ranked in
 // steps of kPChunk keys in order (wave w, round r, lane l holds key
 // (w * kPItems + r) * 64 + l of the step; ballots rank equal digits within
-// a round, per-wave counters across rounds), so equal digits keep their
-// order.
+// a round, per-wave counters across rounds, and each digit's running base
+// carries across steps), so equal digits keep their order.
 __device__ void p_pass(PBuildLds &S, const uint64_t *kin, const int32_t *vin, uint64_t *kout,
                        int32_t *vout, int64_t o, int32_t m, int shift) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -244,14 +247,35 @@ __device__ void p_build_cloud(PBuildLds &S, const PersistArgs &a, const PersistT
       p_pass(S, pt.key, pt.id, a.key2, a.id2, o, m, sh);
       p_pass(S, a.key2, a.id2, pt.key, pt.id, o, m, sh + 8);
     }
-  // coordinates in key order, id -> slot
-  for (int32_t r = t; r < m; r += kPThreads) {
-    const int64_t p = o + r;
-    const int32_t src = pt.id[p];
-    pt.X[p] = a.xyz[src];
-    pt.Y[p] = a.xyz[a.n + src];
-    if (D == 3) pt.Z[p] = a.xyz[2 * a.n + src];
-    a.slot_of[src] = (int32_t)p;
+  // coordinates in key order, id -> slot (four points in flight per thread)
+  for (int32_t r0 = 0; r0 < m; r0 += 4 * kPThreads) {
+    int32_t src[4];
+    double x[4], y[4], z[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t r = r0 + u * kPThreads + t;
+      src[u] = r < m ? pt.id[o + r] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t r = r0 + u * kPThreads + t;
+      if (r < m) {
+        x[u] = a.xyz[src[u]];
+        y[u] = a.xyz[a.n + src[u]];
+        z[u] = D == 3 ? a.xyz[2 * a.n + src[u]] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t r = r0 + u * kPThreads + t;
+      if (r < m) {
+        const int64_t p = o + r;
+        pt.X[p] = x[u];
+        pt.Y[p] = y[u];
+        if (D == 3) pt.Z[p] = z[u];
+        a.slot_of[src[u]] = (int32_t)p;
+      }
+    }
   }
   // split bits between neighbours
   for (int32_t r = t; r + 1 < m; r += kPThreads)
@@ -261,14 +285,29 @@ __device__ void p_build_cloud(PBuildLds &S, const PersistArgs &a, const PersistT
   // that fails the leaf test is internal node o + x, and the splits before
   // a point number its leaf
   const int Li = a.leaf_size ? a.leaf_size[c] : a.L;
+  // split bits of a step and Li on each side in LDS (outside the cloud: a
+  // split above every bit, which ends a scan where the cloud ends)
+  const int H = Li <= kPHalo ? Li : 0;
   int32_t I = 0;
   for (int32_t c0 = 0; c0 < m - 1; c0 += kPThreads) {
     const int32_t r = c0 + t;
+    if (H > 0) {
+      for (int q = t; q < kPThreads + 2 * H; q += kPThreads) {
+        const int64_t y = (int64_t)c0 - H + q;
+        S.sbw[q] = (y >= 0 && y < m - 1) ? a.sb[o + y] : (int8_t)127;
+      }
+      __syncthreads();
+    }
     int32_t f = 0;
     int b = -1;
     if (r < m - 1) {
-      b = a.sb[o + r];
-      f = leaf_test(b, Li, a.sb, o + r, o, o + m - 1);
+      if (H > 0) {
+        b = S.sbw[H + t];
+        f = leaf_test(b, Li, S.sbw, H + t, 0, kPThreads + 2 * H);
+      } else {
+        b = a.sb[o + r];
+        f = leaf_test(b, Li, a.sb, o + r, o, o + m - 1);
+      }
     }
     int32_t total;
     const int32_t ex = p_exscan(f, S, total);
@@ -366,9 +405,16 @@ constexpr size_t persist_lds_bytes(int waves) {
   return q > sizeof(PBuildLds) ? q : sizeof(PBuildLds);
 }
 
+// Register caps of the all-points kernel that leave room for the build
+// code (the k = 10 and 12 caps of 80 and 96 VGPRs would spill it).
+template <int K>
+constexpr int persist_min_waves() {
+  return K == 20 || K == 24 || K == 32 ? 3 : 1;
+}
+
 template <int D, int K>
 __global__ void __launch_bounds__(kPThreads)
-    __attribute__((amdgpu_waves_per_eu(knn_all_min_waves<K>())))
+    __attribute__((amdgpu_waves_per_eu(persist_min_waves<K>())))
         k_forest_persistent(PersistArgs a, PersistTree pt, TreeView t, int qwaves) {
   extern __shared__ __align__(16) char smem[];
   PBuildLds &S = *reinterpret_cast<PBuildLds *>(smem);
