@@ -501,7 +501,13 @@ __device__ __forceinline__ bool ball_inside(double px, double py, double pz, con
 __device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // sorted positions scored on either side of a query group before its walk
-constexpr int64_t kPrescore = 32;
+// (all-points rows), per k bucket: 48 for the LDS-heap buckets (3% faster
+// than 32 at k = 64), 32 elsewhere (48, 64 and 96 measured no faster for
+// k = 32-50, 96 slower)
+template <int K>
+constexpr int64_t prescore_reach() {
+  return K >= 64 ? 48 : 32;
+}
 
 // maximum of v over the wavefront (every lane gets it)
 __device__ __forceinline__ int wave_max(int v) {
@@ -587,7 +593,7 @@ struct WaveSearch {
   // insertions would.
   __device__ __forceinline__ void prescore_near_first(int64_t a, int64_t b, int64_t own, int k) {
     const int lane = threadIdx.x & 63;
-    const int cnt = (int)(b - a + 1);  // <= 64 + 2 kPrescore entries of the stage
+    const int cnt = (int)(b - a + 1);  // <= 64 + 2 prescore_reach<K>() entries of the stage
     for (int j = lane; j < cnt; j += 64) {
       Cand q;
       q.x = t.X[a + j];
@@ -807,7 +813,7 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t h, uint32_t nb) {
 // register candidate sets, 64 entries for the LDS heaps), plus the heap
 template <int K>
 constexpr size_t wave_lds_bytes() {
-  return (HeapFor<K>::shared_prescore ? 64 : 64 + 2 * kPrescore) * sizeof(Cand) +
+  return (HeapFor<K>::shared_prescore ? 64 : 64 + 2 * prescore_reach<K>()) * sizeof(Cand) +
          (size_t)HeapFor<K>::lds_slots * 64 * (sizeof(double) + sizeof(int32_t));
 }
 
@@ -827,7 +833,7 @@ __device__ __forceinline__ void bind_lds(WaveSearch<D, K, E, P> &s, char *smem, 
   char *base = smem + (size_t)w * wave_lds_bytes<K>();
   s.stage = reinterpret_cast<Cand *>(base);
   if constexpr (HeapFor<K>::lds_slots > 0) {
-    constexpr int kStage = HeapFor<K>::shared_prescore ? 64 : 64 + 2 * kPrescore;
+    constexpr int kStage = HeapFor<K>::shared_prescore ? 64 : 64 + 2 * prescore_reach<K>();
     double *hd = reinterpret_cast<double *>(base + kStage * sizeof(Cand));
     s.h.bind(hd, reinterpret_cast<int32_t *>(hd + (size_t)HeapFor<K>::lds_slots * 64));
   }
@@ -874,13 +880,15 @@ __device__ __forceinline__ void all_points_group(const TreeView &t, int k,
   s.key_ref = (s.key_ref << 32) | (uint32_t)uni((int32_t)t.key[g0 + mid]);
   s.h.init(k, s.valid);
   // score first the sorted positions around the group, within its cloud:
-  // the group's own points and kPrescore on either side (Morton neighbours
+  // the group's own points and prescore_reach<K>() on either side (Morton neighbours
   // of every lane).  This tightens every lane's k-th distance before the
   // walk, which then skips these positions.
   if constexpr (HeapFor<K>::shared_prescore)
-    s.prescore(max(c_lo, g0 - kPrescore), min(c_hi, last + kPrescore), g0 + lane);
+    s.prescore(max(c_lo, g0 - prescore_reach<K>()), min(c_hi, last + prescore_reach<K>()),
+               g0 + lane);
   else
-    s.prescore_near_first(max(c_lo, g0 - kPrescore), min(c_hi, last + kPrescore), g0 + lane, k);
+    s.prescore_near_first(max(c_lo, g0 - prescore_reach<K>()),
+                          min(c_hi, last + prescore_reach<K>()), g0 + lane, k);
   // lowest common ancestor of the group's leaves
   const int32_t lf = uni(t.leaf_of[g0]), ll = uni(t.leaf_of[last]);
   int32_t G = ~lf;
