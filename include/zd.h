@@ -296,7 +296,9 @@ ZD_API zd_status zd_forest_build(const zd_params *params, const double *xyz, int
 
 /* All-points k-NN rows of every cloud: row i (i < n) holds the k nearest
  * points of point i's cloud other than i, as zd_knn.  out_ids/out_d2:
- * (device) [n][k].  Asynchronous.  Errors: ZD_EINVAL, ZD_EKMAX, ZD_EDEVICE. */
+ * (device) [n][k].  Asynchronous.  On a plan (zd_forest_plan*), the trees
+ * of its last zd_forest_run, ordered on the stream of that run.  Errors:
+ * ZD_EINVAL (also for a plan that has not run yet), ZD_EKMAX, ZD_EDEVICE. */
 ZD_API zd_status zd_forest_knn(zd_forest forest, int32_t k, int32_t *out_ids, double *out_d2,
                                void *stream);
 

@@ -1091,6 +1091,7 @@ struct zd_forest_s {
   int32_t C = 0;
   const double *xyz = nullptr;  // the caller's points (read by every build)
   bool have_box = false;
+  bool built = false;           // a build has been issued (a plan: its first run)
   double box_lo[3] = {0, 0, 0}, box_hi[3] = {0, 0, 0};
   int64_t *offsets = nullptr;   // device [C+1]
   int32_t *seg = nullptr;       // device [n]: cloud of each position
@@ -1294,12 +1295,14 @@ zd_status zd_forest_build(const zd_params *params, const double *xyz, int64_t n,
     forest_destroy(f);
     return to_status(e);
   }
+  f->built = true;
   *out = f;
   return ZD_OK;
 }
 
 zd_status zd_forest_knn(zd_forest f, int32_t k, int32_t *out_ids, double *out_d2, void *stream) {
   if (!f || k < 1) return ZD_EINVAL;
+  if (!f->built) return ZD_EINVAL;  // a plan's trees exist after its first run
   if (k > ZD_KMAX) return ZD_EKMAX;
   if (f->t->broken) return ZD_EDEVICE;
   if (f->t->st.n > 0 && (!out_ids || !out_d2)) return ZD_EINVAL;
@@ -1472,6 +1475,7 @@ zd_status zd_forest_run(zd_forest f, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = bind_stream(f->t, s);
   if (e == hipSuccess) e = hipGraphLaunch(f->exec, s);
+  if (e == hipSuccess) f->built = true;
   return to_status(e);
 }
 

@@ -51,6 +51,23 @@ def test_persistent_leaf_sizes_and_box():
         plan.close()
 
 
+def test_plan_queries_need_a_run():
+    """A plan's trees exist only after its first run: an eager query before
+    it is refused instead of walking unbuilt arrays."""
+    P, off = mixed_clouds(34)
+    for persistent in (False, True):
+        plan = zd.ZdForestPlan(dev(P), off, 8, leaf_size=16, persistent=persistent)
+        ids = torch.empty_like(plan.ids)
+        d2 = torch.empty_like(plan.d2)
+        with pytest.raises(zd.ZdError):
+            zd.zd_forest_knn(plan._h, 8, ids, d2)
+        run(plan)
+        zd.zd_forest_knn(plan._h, 8, ids, d2)
+        torch.cuda.synchronize()
+        same((ids, d2), oracle_rows(P, off, 8), f"after the first run ({persistent})")
+        plan.close()
+
+
 def test_persistent_replays_and_eager_queries():
     P, off = mixed_clouds(32)
     xyz = dev(P)
