@@ -428,15 +428,22 @@ hipError_t insert_small_prepare(zd_tree t, const double *xyz, int64_t m, SmallIn
   }
   e = dev_alloc_n(&w.bk, m, s);
   if (e == hipSuccess) e = dev_alloc_n(&w.bi, m, s);
-  if (e == hipSuccess) e = dev_alloc_n(&w.bk2, m, s);
-  if (e == hipSuccess) e = dev_alloc_n(&w.bi2, m, s);
   if (e == hipSuccess) e = dev_alloc_n(&w.leaf, m, s);
   if (e == hipSuccess) e = dev_alloc_n(&w.path, m * kMaxPath, s);
   if (e == hipSuccess) e = dev_alloc_n(&w.depth, m, s);
-  if (e == hipSuccess) e = encode_keys(t->geo, xyz, m, m, (int32_t)t->cap, w.bk, w.bi, s);
+  if (e == hipSuccess && m <= kSmallSortKeys)
+    // box check, keys, sort, descent and room check in one launch
+    return insert_in_place_prepare(t->geo, t->geo.lo, t->hi, xyz, m, (int32_t)t->cap,
+                                   t->st.inode, t->st.key, t->st.leaf_begin, t->meta,
+                                   pd.ovf_blk, pd.ovf_cnt, w.bk, w.bi, w.leaf, w.path, w.depth,
+                                   s);
+  if (e == hipSuccess) e = dev_alloc_n(&w.bk2, m, s);
+  if (e == hipSuccess) e = dev_alloc_n(&w.bi2, m, s);
+  if (e == hipSuccess) e = fill_i32(t->meta + kMetaCheck, 0, 1, s);
   if (e == hipSuccess)
-    e = m <= kSmallSortKeys ? sort_pairs_small(w.bk, w.bi, m, s)
-                            : radix_sort_pairs(w.bk, w.bi, w.bk2, w.bi2, m, dim * t->geo.B, s);
+    e = count_outside_box(dim, xyz, m, t->geo.lo, t->hi, t->meta + kMetaCheck, s);
+  if (e == hipSuccess) e = encode_keys(t->geo, xyz, m, m, (int32_t)t->cap, w.bk, w.bi, s);
+  if (e == hipSuccess) e = radix_sort_pairs(w.bk, w.bi, w.bk2, w.bi2, m, dim * t->geo.B, s);
   if (e == hipSuccess) e = fill_i32(t->meta + kMetaLocal, 0, 2, s);
   if (e == hipSuccess)
     e = insert_in_place_locate(t->st.inode, t->st.key, t->st.leaf_begin, t->meta, w.bk, m,
@@ -450,14 +457,14 @@ bool small_fits(const zd_tree t, const int32_t *meta) {
 }
 
 hipError_t insert_small_commit(zd_tree t, const double *xyz, int64_t m, const SmallInsert &w,
-                               const int32_t *meta) {
+                               const int32_t *meta, int32_t *out_new_ids) {
   hipStream_t s = t->stream;
   zd_tree_s::Pending &pd = t->pend;
   hipError_t e = grow_ids(t, t->cap + m);
   if (e == hipSuccess)
     e = insert_in_place_commit(t->dim, w.leaf, m, w.path, w.depth, w.bi, xyz, (int32_t)t->cap,
                                pd.ovf_blk, pd.ovf_cnt, pd.blocks, pd.pxyz, pd.pcap, pd.pid,
-                               t->slot_of, t->st.inode, t->root_box, s);
+                               t->slot_of, t->st.inode, t->root_box, out_new_ids, s);
   if (e == hipSuccess) {
     pd.nblocks += meta[kMetaBlocks];
     pd.n_pool += m;
@@ -659,10 +666,13 @@ zd_status zd_insert_batch(zd_tree t, const double *xyz, int64_t m, int32_t *out_
   const bool small = t->st.n > 0 && m <= pool_blocks_for(t->st.n);
   SmallInsert w;
   int32_t meta[kMetaCount];
-  if (e == hipSuccess) e = fill_i32(t->meta + kMetaCheck, 0, 1, s);
-  if (e == hipSuccess)
-    e = count_outside_box(dim, xyz, m, t->geo.lo, t->hi, t->meta + kMetaCheck, s);
-  if (e == hipSuccess && small) e = insert_small_prepare(t, xyz, m, w);
+  if (e == hipSuccess && small) {
+    e = insert_small_prepare(t, xyz, m, w);  // (checks the box too)
+  } else {
+    if (e == hipSuccess) e = fill_i32(t->meta + kMetaCheck, 0, 1, s);
+    if (e == hipSuccess)
+      e = count_outside_box(dim, xyz, m, t->geo.lo, t->hi, t->meta + kMetaCheck, s);
+  }
   if (e != hipSuccess) {
     small_release(t, w);
     t->broken = true;
@@ -677,9 +687,8 @@ zd_status zd_insert_batch(zd_tree t, const double *xyz, int64_t m, int32_t *out_
   // 2a. a small batch goes into its leaves in place (Algorithm 4 without
   // rewriting the sorted arrays) when every point's leaf has room
   if (small && small_fits(t, meta)) {
-    e = insert_small_commit(t, xyz, m, w, meta);
+    e = insert_small_commit(t, xyz, m, w, meta, out_new_ids);  // (writes the new ids too)
     small_release(t, w);
-    if (e == hipSuccess && out_new_ids) e = iota_i32(out_new_ids, first_id, m, s);
     if (e != hipSuccess) {
       t->broken = true;
       return to_status(e);

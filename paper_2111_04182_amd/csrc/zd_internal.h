@@ -447,7 +447,17 @@ hipError_t insert_in_place_commit(int dim, const int32_t *leaf, int64_t m, const
                                   int32_t id_base, int32_t *ovf_blk, int32_t *ovf_cnt,
                                   int32_t *blocks_used, double *pxyz, int64_t pcap, int32_t *pid,
                                   int32_t *slot_of, INode *inode, double *root_box,
-                                  hipStream_t s);
+                                  int32_t *new_ids, hipStream_t s);
+// One launch for a batch of at most kSmallSortKeys points: the box check,
+// keys, sort, descent with paths and room check of the two calls above
+// (counts to meta[kMetaCheck], meta[kMetaLocal], meta[kMetaBlocks]).
+hipError_t insert_in_place_prepare(const Geometry &g, const double *lo, const double *hi,
+                                   const double *xyz, int64_t m, int32_t id_base,
+                                   const INode *inode, const uint64_t *tkey,
+                                   const int32_t *leaf_begin, int32_t *meta,
+                                   const int32_t *ovf_blk, const int32_t *ovf_cnt, uint64_t *bk,
+                                   int32_t *bi, int32_t *leaf, int32_t *path, int32_t *depth,
+                                   hipStream_t s);
 hipError_t tombstone_ids(const int32_t *ids, int64_t m, int32_t *slot_of, int32_t *mark,
                          double *X, double *pX, hipStream_t s);
 // live flags of the sorted slots and the pool entries, scanned (positions

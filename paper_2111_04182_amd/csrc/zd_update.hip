@@ -12,6 +12,8 @@
 // Every step is a coalesced O(n + m) sweep at HBM bandwidth.
 #include "zd_internal.h"
 
+#include <algorithm>
+
 namespace zd {
 
 // --------------------------------------------------------- bounds / boxes --
@@ -335,15 +337,14 @@ namespace zd {
 // it suffices to compare the key with one point of the leaf above the
 // split bit of the leaf's parent (every point of an ancestor shares that
 // leaf point's bits above the ancestor's higher split bit).
-__global__ void k_ins_locate(const INode *__restrict__ inode, const uint64_t *__restrict__ tkey,
-                             const int32_t *__restrict__ leaf_begin, const int32_t *meta,
-                             const uint64_t *__restrict__ bk, int64_t m,
-                             int32_t *__restrict__ leaf_out, int32_t *__restrict__ path,
-                             int32_t *__restrict__ depth_out, int32_t *local_fail) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m) return;
-  const uint64_t key = bk[j];
-  int32_t x = meta[kMetaRoot];
+__device__ __forceinline__ bool ins_locate_one(const INode *__restrict__ inode,
+                                               const uint64_t *__restrict__ tkey,
+                                               const int32_t *__restrict__ leaf_begin,
+                                               int32_t root, uint64_t key, int64_t j,
+                                               int32_t *__restrict__ leaf_out,
+                                               int32_t *__restrict__ path,
+                                               int32_t *__restrict__ depth_out) {
+  int32_t x = root;
   bool ok = x != kNoRoot;
   int d = 0, last_bit = 64;
   for (; ok && x >= 0; ++d) {
@@ -360,23 +361,144 @@ __global__ void k_ins_locate(const INode *__restrict__ inode, const uint64_t *__
   if (ok && last_bit < 63 && ((key ^ tkey[leaf_begin[~x]]) >> (last_bit + 1)) != 0) ok = false;
   leaf_out[j] = ok ? ~x : -1;
   depth_out[j] = ok ? d : 0;
-  if (!ok) atomicAdd(local_fail, 1);
+  return ok;
+}
+
+__global__ void k_ins_locate(const INode *__restrict__ inode, const uint64_t *__restrict__ tkey,
+                             const int32_t *__restrict__ leaf_begin, const int32_t *meta,
+                             const uint64_t *__restrict__ bk, int64_t m,
+                             int32_t *__restrict__ leaf_out, int32_t *__restrict__ path,
+                             int32_t *__restrict__ depth_out, int32_t *local_fail) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  if (!ins_locate_one(inode, tkey, leaf_begin, meta[kMetaRoot], bk[j], j, leaf_out, path,
+                      depth_out))
+    atomicAdd(local_fail, 1);
 }
 
 // One thread per run of batch points bound for one leaf (the batch is
 // sorted by key, and leaves hold consecutive key ranges): the run must fit
 // in the leaf's block; count the leaves that need a new block.
-__global__ void k_ins_runs(const int32_t *__restrict__ leaf, int64_t m,
-                           const int32_t *__restrict__ ovf_blk, const int32_t *__restrict__ ovf_cnt,
-                           int32_t *local_fail, int32_t *blocks_needed) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m) return;
+__device__ __forceinline__ void ins_run_check(const int32_t *leaf, int64_t m, int64_t j,
+                                              const int32_t *__restrict__ ovf_blk,
+                                              const int32_t *__restrict__ ovf_cnt,
+                                              int32_t *local_fail, int32_t *blocks_needed) {
   const int32_t l = leaf[j];
   if (l < 0 || (j > 0 && leaf[j - 1] == l)) return;
   int64_t r = 1;
   while (j + r < m && leaf[j + r] == l) ++r;
   if (ovf_cnt[l] + r > kOvfBlock) atomicAdd(local_fail, 1);
   if (ovf_blk[l] < 0) atomicAdd(blocks_needed, 1);
+}
+
+__global__ void k_ins_runs(const int32_t *__restrict__ leaf, int64_t m,
+                           const int32_t *__restrict__ ovf_blk, const int32_t *__restrict__ ovf_cnt,
+                           int32_t *local_fail, int32_t *blocks_needed) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  ins_run_check(leaf, m, j, ovf_blk, ovf_cnt, local_fail, blocks_needed);
+}
+
+// A batch of at most kSmallSortKeys points in one workgroup and one launch:
+// the declared-box check, keys (ids id_base, id_base + 1, ...), the sort by
+// (key, id) in LDS (a bitonic network), the descent of every point with its
+// path, and the per-leaf room check.  The three counts go to
+// meta[kMetaCheck], meta[kMetaLocal] and meta[kMetaBlocks].
+template <int D>
+__global__ void __launch_bounds__(1024)
+    k_ins_prepare(Geometry g, Box3 box, const double *__restrict__ xyz, int m, int np2,
+                  int32_t id_base, const INode *__restrict__ inode,
+                  const uint64_t *__restrict__ tkey, const int32_t *__restrict__ leaf_begin,
+                  int32_t *meta, const int32_t *__restrict__ ovf_blk,
+                  const int32_t *__restrict__ ovf_cnt, uint64_t *__restrict__ bk,
+                  int32_t *__restrict__ bi, int32_t *__restrict__ leaf,
+                  int32_t *__restrict__ path, int32_t *__restrict__ depth) {
+  __shared__ uint64_t sk[kSmallSortKeys];
+  __shared__ int32_t sv[kSmallSortKeys];
+  __shared__ int32_t sl[kSmallSortKeys];
+  __shared__ int32_t cnt[3];  // outside the box, no room in place, new blocks
+  const int t = threadIdx.x;
+  if (t < 3) cnt[t] = 0;
+  __syncthreads();
+  for (int i = t; i < np2; i += blockDim.x) {
+    if (i < m) {
+      const double x = xyz[i], y = xyz[m + i], z = D == 3 ? xyz[2 * m + i] : 0.0;
+      bool bad = !(x >= box.lo[0] && x <= box.hi[0]) || !(y >= box.lo[1] && y <= box.hi[1]);
+      if (D == 3) bad = bad || !(z >= box.lo[2] && z <= box.hi[2]);
+      if (bad) atomicAdd(&cnt[0], 1);
+      sk[i] = morton_key<D>(g, x, y, z);
+      sv[i] = id_base + i;
+    } else {
+      sk[i] = ~uint64_t(0);
+      sv[i] = INT_MAX;
+    }
+  }
+  __syncthreads();
+  for (int size = 2; size <= np2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = t; i < np2 / 2; i += blockDim.x) {
+        const int a = 2 * stride * (i / stride) + (i % stride);
+        const int b = a + stride;
+        const bool up = (a & size) == 0;
+        const uint64_t ka = sk[a], kb = sk[b];
+        const int32_t va = sv[a], vb = sv[b];
+        const bool b_first = kb < ka || (kb == ka && vb < va);
+        if (b_first == up) {
+          sk[a] = kb;
+          sk[b] = ka;
+          sv[a] = vb;
+          sv[b] = va;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int32_t root = meta[kMetaRoot];
+  for (int j = t; j < m; j += blockDim.x) {
+    bk[j] = sk[j];
+    bi[j] = sv[j];
+    if (!ins_locate_one(inode, tkey, leaf_begin, root, sk[j], j, leaf, path, depth))
+      atomicAdd(&cnt[1], 1);
+    sl[j] = leaf[j];
+  }
+  __syncthreads();
+  for (int j = t; j < m; j += blockDim.x) ins_run_check(sl, m, j, ovf_blk, ovf_cnt, &cnt[1], &cnt[2]);
+  __syncthreads();
+  if (t == 0) {
+    meta[kMetaCheck] = cnt[0];
+    meta[kMetaLocal] = cnt[1];
+    meta[kMetaBlocks] = cnt[2];
+  }
+}
+
+hipError_t insert_in_place_prepare(const Geometry &g, const double *lo, const double *hi,
+                                   const double *xyz, int64_t m, int32_t id_base,
+                                   const INode *inode, const uint64_t *tkey,
+                                   const int32_t *leaf_begin, int32_t *meta,
+                                   const int32_t *ovf_blk, const int32_t *ovf_cnt, uint64_t *bk,
+                                   int32_t *bi, int32_t *leaf, int32_t *path, int32_t *depth,
+                                   hipStream_t s) {
+  if (m <= 0 || m > kSmallSortKeys) return hipErrorInvalidValue;
+  int np2 = 2;
+  while (np2 < m) np2 <<= 1;
+  Box3 box{};
+  for (int c = 0; c < g.dim; ++c) {
+    box.lo[c] = lo[c];
+    box.hi[c] = hi[c];
+  }
+  // a thread per point for the descents (up to 1,024), at least one per
+  // compare-exchange pair of the network
+  const int want = (int)std::max<int64_t>(m, np2 / 2);
+  const int threads = want < 1024 ? (want + 63) / 64 * 64 : 1024;
+  if (g.dim == 3)
+    k_ins_prepare<3><<<1, threads, 0, s>>>(g, box, xyz, (int)m, np2, id_base, inode, tkey,
+                                           leaf_begin, meta, ovf_blk, ovf_cnt, bk, bi, leaf,
+                                           path, depth);
+  else
+    k_ins_prepare<2><<<1, threads, 0, s>>>(g, box, xyz, (int)m, np2, id_base, inode, tkey,
+                                           leaf_begin, meta, ovf_blk, ovf_cnt, bk, bi, leaf,
+                                           path, depth);
+  return hipGetLastError();
 }
 
 // FP64 atomic min / max in L2 (global_atomic_min_f64 / max_f64 on gfx950;
@@ -402,7 +524,8 @@ __global__ void __launch_bounds__(64)
                  const int32_t *__restrict__ depth, const int32_t *__restrict__ bi,
                  const double *__restrict__ bxyz, int64_t nb, int32_t id_base, int32_t *ovf_blk,
                  int32_t *ovf_cnt, int32_t *blocks_used, double *pxyz, int64_t pcap,
-                 int32_t *pid, int32_t *slot_of, INode *inode, double *root_box) {
+                 int32_t *pid, int32_t *slot_of, INode *inode, double *root_box,
+                 int32_t *new_ids) {
   const int64_t j = blockIdx.x;
   const int lane = threadIdx.x;
   const int32_t l = leaf[j];
@@ -429,6 +552,7 @@ __global__ void __launch_bounds__(64)
       }
       pid[e] = id;
       slot_of[id] = kPoolSlot + (int32_t)e;
+      if (new_ids) new_ids[src] = id;
     }
     ovf_cnt[l] = c0 + (int32_t)r;
 #pragma unroll
@@ -475,18 +599,18 @@ hipError_t insert_in_place_commit(int dim, const int32_t *leaf, int64_t m, const
                                   int32_t id_base, int32_t *ovf_blk, int32_t *ovf_cnt,
                                   int32_t *blocks_used, double *pxyz, int64_t pcap, int32_t *pid,
                                   int32_t *slot_of, INode *inode, double *root_box,
-                                  hipStream_t s) {
+                                  int32_t *new_ids, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   static_assert(kMaxPath <= 64, "one lane per path level");
   const unsigned grid = (unsigned)m;
   if (dim == 3)
     k_ins_commit<3><<<grid, 64, 0, s>>>(leaf, m, path, depth, bi, bxyz, m, id_base, ovf_blk,
                                         ovf_cnt, blocks_used, pxyz, pcap, pid, slot_of, inode,
-                                        root_box);
+                                        root_box, new_ids);
   else
     k_ins_commit<2><<<grid, 64, 0, s>>>(leaf, m, path, depth, bi, bxyz, m, id_base, ovf_blk,
                                         ovf_cnt, blocks_used, pxyz, pcap, pid, slot_of, inode,
-                                        root_box);
+                                        root_box, new_ids);
   return hipGetLastError();
 }
 
