@@ -641,7 +641,9 @@ def leg_grad(fd_coords=1000):
     pts = P.copy()
     live = np.ones(n0, dtype=bool)
     tree = zd.ZdTree(zd.soa(torch.from_numpy(P)), 16, box=W.UNIT3)
-    times = {"forward": [], "backward": [], "autograd_backward": [], "insert": [], "delete": []}
+    times = {"forward": [], "backward": [], "backward_tree_order": [], "autograd_backward": [],
+             "insert": [], "delete": []}
+    tree_vs_id_order = 0.0
     worst = 0.0
     checked = 0
     for r in range(len(inserts)):
@@ -665,6 +667,17 @@ def leg_grad(fd_coords=1000):
         e[1].record()
         torch.cuda.synchronize()
         times["backward"].append(e[0].elapsed_time(e[1]))
+        # the same in the tree's Morton order (while no in-place batch is
+        # pending, as after the build and after a fold)
+        if tree.pending() == (0, 0):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e[0].record()
+            gt = tree.knn_backward(ids, g)
+            e[1].record()
+            torch.cuda.synchronize()
+            times["backward_tree_order"].append(e[0].elapsed_time(e[1]))
+            tree_vs_id_order = max(tree_vs_id_order, float((gt - gx).abs().max() /
+                                                           gx.abs().max().clamp(min=1.0)))
         # the autograd function end to end (torch's masking and sum included)
         xg = xyz.clone().requires_grad_(True)
         e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -716,10 +729,11 @@ def leg_grad(fd_coords=1000):
         live[D] = False
     tree.check()
     tree.close()
-    med = {kk: float(np.median(v)) for kk, v in times.items()}
+    med = {kk: float(np.median(v)) if v else None for kk, v in times.items()}
     return {"n": n0, "k": k, "median_ms": med, "fwd_bwd_points_per_s":
             n0 / (med["forward"] + med["backward"]) * 1e3, "fd_checked": checked,
-            "fd_max_rel_err": worst}
+            "fd_max_rel_err": worst, "backward_tree_order_rounds": len(times["backward_tree_order"]),
+            "backward_tree_vs_id_order_max_rel_diff": tree_vs_id_order}
 
 
 def bench_spheres(args):

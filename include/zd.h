@@ -276,6 +276,21 @@ ZD_API zd_status zd_knn_backward_det(int32_t dim, const double *xyz, int64_t str
                                      int64_t rows, int32_t k, const int32_t *ids,
                                      const double *grad_d2, double *grad_xyz, void *stream);
 
+/* zd_knn_backward for the tree's own all-points rows, taken in the tree's
+ * Morton order: the terms between points of one 1,024-point Morton tile
+ * are summed in LDS and only the others by atomics, into a buffer in
+ * sorted order, so most atomics stay on chip and near each other.  The
+ * points are the tree's current ones (xyz by id, as given to zd_build and
+ * the inserts); ids/grad_d2: (device) [cap][k], the rows of zd_knn(t,
+ * NULL, cap, k, ...) on this tree, unchanged since; grad_xyz: (device)
+ * [dim][cap], overwritten (zero for dead ids).  Results equal
+ * zd_knn_backward's up to the order of the floating-point additions.
+ * Read-only on the tree (may run beside queries, as zd_knn).  Errors:
+ * ZD_EINVAL (also while in-place small batches are pending: use
+ * zd_knn_backward then), ZD_EKMAX, ZD_EDEVICE. */
+ZD_API zd_status zd_knn_backward_tree(zd_tree tree, int32_t k, const int32_t *ids,
+                                      const double *grad_d2, double *grad_xyz, void *stream);
+
 /* Batched forest: C independent point clouds answered in one pass (an
  * addition beyond the paper, which builds one tree).  Cloud c is points
  * [offsets[c], offsets[c+1]) of xyz; point i keeps id i.  Every cloud gets

@@ -21,7 +21,7 @@ ZD_OK, ZD_EINVAL, ZD_EBOUNDS, ZD_EID, ZD_ENOMEM, ZD_EDEVICE, ZD_EKMAX, ZD_ELIMIT
 ZD_KMAX = 100
 
 EXPORTED = ("zd_build", "zd_knn", "zd_knn_root", "zd_knn_noalloc", "zd_insert_batch", "zd_delete_batch", "zd_free", "zd_info",
-            "zd_check", "zd_pending", "zd_set_walk_limit", "zd_export", "zd_knn_backward", "zd_knn_backward_det", "zd_forest_build", "zd_forest_knn", "zd_forest_plan",
+            "zd_check", "zd_pending", "zd_set_walk_limit", "zd_export", "zd_knn_backward", "zd_knn_backward_det", "zd_knn_backward_tree", "zd_forest_build", "zd_forest_knn", "zd_forest_plan",
             "zd_forest_plan_persistent",
             "zd_forest_run", "zd_forest_check", "zd_forest_free", "zd_status_str")
 
@@ -79,6 +79,8 @@ def lib() -> C.CDLL:
         L.zd_export.argtypes = [vp] * 11
         L.zd_knn_backward_det.restype = C.c_int
         L.zd_knn_backward_det.argtypes = [i32, vp, i64, i64, i32, vp, vp, vp, vp]
+        L.zd_knn_backward_tree.restype = C.c_int
+        L.zd_knn_backward_tree.argtypes = [vp, i32, vp, vp, vp, vp]
         L.zd_knn_backward.restype = C.c_int
         L.zd_knn_backward.argtypes = [i32, vp, i64, i64, i32, vp, vp, vp, vp]
         L.zd_forest_build.restype = C.c_int
@@ -259,6 +261,23 @@ def zd_knn_backward(xyz: torch.Tensor, ids: torch.Tensor, grad_d2: torch.Tensor,
     return grad_xyz
 
 
+def zd_knn_backward_tree(tree, dim: int, cap: int, ids: torch.Tensor, grad_d2: torch.Tensor,
+                         grad_xyz: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """zd_knn_backward for the tree's own all-points rows ids [cap, k], in the
+    tree's Morton order (tree: a zd_tree handle with no pending in-place
+    batches).  Returns the gradient as SoA (dim, cap)."""
+    rows, k = ids.shape
+    if rows != cap:
+        raise ValueError("ids must hold one row per id of the tree")
+    if grad_xyz is None:
+        grad_xyz = torch.empty((dim, cap), dtype=torch.float64, device="cuda")
+    ids = ids.contiguous()
+    grad_d2 = grad_d2.to(torch.float64).contiguous()
+    _check(lib().zd_knn_backward_tree(tree, k, _dptr(ids), _dptr(grad_d2), _dptr(grad_xyz),
+                                      _stream(stream)), "zd_knn_backward_tree")
+    return grad_xyz
+
+
 # --------------------------------------------------------------------------
 # convenience object
 # --------------------------------------------------------------------------
@@ -272,6 +291,7 @@ class ZdTree:
         self.leaf_size = leaf_size
         self._h = zd_build(xyz, leaf_size, box, shift_seed, shift, stream, query_waves)
         self.cap = xyz.shape[1]  # id capacity, tracked here to avoid a sync
+        self.version = 0  # counts the updates (a backward checks its rows are current)
 
     @property
     def handle(self):
@@ -302,10 +322,17 @@ class ZdTree:
         out = torch.empty(xyz.shape[1], dtype=torch.int32, device="cuda")
         zd_insert_batch(self._h, xyz, out, stream)
         self.cap += xyz.shape[1]
+        self.version += 1
         return out
 
     def delete(self, ids: torch.Tensor, stream=None):
         zd_delete_batch(self._h, ids.to(device="cuda", dtype=torch.int32).contiguous(), stream)
+        self.version += 1
+
+    def knn_backward(self, ids: torch.Tensor, grad_d2: torch.Tensor, stream=None) -> torch.Tensor:
+        """Gradient of sum(grad_d2 * d2) over this tree's all-points rows ids
+        (unchanged since knn), w.r.t. its points by id, in its Morton order."""
+        return zd_knn_backward_tree(self._h, self.dim, self.cap, ids, grad_d2, None, stream)
 
     def export(self) -> dict:
         return zd_export(self._h, self.dim)

@@ -4,10 +4,14 @@
 k-NN rows of ``tree``; d2 is differentiable with respect to the SoA point
 tensor ``xyz`` (d, cap), which must hold the tree's points by id.  The
 neighbour set is chosen exactly and held fixed: the backward pass is the
-library's scatter-add kernel (zd_knn_backward),
+library's scatter-add kernel,
     dL/dp += 2 (p - q) g,   dL/dq -= 2 (p - q) g,
-for every row p, neighbour q and upstream gradient g.  Selection itself is
-not differentiated, as usual for nearest-neighbour losses.
+for every row p, neighbour q and upstream gradient g: in the tree's Morton
+order (zd_knn_backward_tree) when the tree is unchanged since the forward
+pass and holds no in-place batches, else over the rows in id order
+(zd_knn_backward), or without atomics in a fixed order when
+deterministic=True (zd_knn_backward_det).  Selection itself is not
+differentiated, as usual for nearest-neighbour losses.
 """
 from __future__ import annotations
 
@@ -23,6 +27,8 @@ class ZdKnnSqDist(torch.autograd.Function):
         ctx.save_for_backward(xyz, ids)
         ctx.mark_non_differentiable(ids)
         ctx.deterministic = deterministic
+        ctx.tree = tree
+        ctx.version = tree.version
         return d2, ids
 
     @staticmethod
@@ -30,7 +36,12 @@ class ZdKnnSqDist(torch.autograd.Function):
         xyz, ids = ctx.saved_tensors
         g = torch.zeros(ids.shape, dtype=torch.float64, device=xyz.device) if grad_d2 is None \
             else grad_d2.contiguous()
-        grad = zd_knn_backward(xyz.detach(), ids, g, deterministic=ctx.deterministic)
+        tree = ctx.tree
+        if (not ctx.deterministic and tree.handle is not None and tree.version == ctx.version
+                and tree.cap == xyz.shape[1] and tree.pending() == (0, 0)):
+            grad = tree.knn_backward(ids, g)
+        else:
+            grad = zd_knn_backward(xyz.detach(), ids, g, deterministic=ctx.deterministic)
         return grad, None, None, None
 
 

@@ -629,6 +629,21 @@ zd_status zd_knn(zd_tree t, const double *q_xyz, int64_t m, int32_t k, int32_t *
   return ZD_OK;
 }
 
+zd_status zd_knn_backward_tree(zd_tree t, int32_t k, const int32_t *ids,
+                               const double *grad_d2, double *grad_xyz, void *stream) {
+  if (!t || k < 1) return ZD_EINVAL;
+  if (k > ZD_KMAX) return ZD_EKMAX;
+  if (t->broken) return ZD_EDEVICE;
+  if (t->pend.any()) return ZD_EINVAL;  // in-place batches pending: zd_knn_backward applies
+  if (t->cap > 0 && (!ids || !grad_d2 || !grad_xyz)) return ZD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = join_query_stream(t, s, false);
+  if (e == hipSuccess && t->cap > 0)
+    e = knn_backward_tree(t->dim, t->view(), t->slot_of, t->cap, k, ids, grad_d2, grad_xyz, s);
+  if (e == hipSuccess) e = join_query_stream(t, s, true);
+  return to_status(e);
+}
+
 zd_status zd_knn_root(zd_tree t, const double *q_xyz, int64_t m, int32_t k, int32_t *out_ids,
                       double *out_d2, void *stream) {
   if (!t || m < 0 || k < 1) return ZD_EINVAL;

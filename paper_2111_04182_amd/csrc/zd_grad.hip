@@ -160,3 +160,97 @@ hipError_t knn_backward_det(int dim, const double *xyz, int64_t stride, int64_t 
 }
 
 }  // namespace zd
+
+namespace zd {
+
+// ---------------------------------------------------------------------------
+// The same gradient for the all-points rows of a tree, taken in the tree's
+// Morton order: workgroup w takes sorted positions [kBwdTile w,
+// kBwdTile (w + 1)).  A row's neighbours are mostly Morton neighbours, so
+// most of its neighbour terms fall on points of the same tile: those are
+// summed in LDS, and only the rest are added in device memory, into a
+// buffer in sorted order (near the row's own position, not at a random id).
+// The tile's sums then go to that buffer once per point, and a last pass
+// writes each sorted position's sum to its id.
+// ---------------------------------------------------------------------------
+constexpr int kBwdTile = 1024;
+
+template <int D>
+__global__ void __launch_bounds__(kBwdTile)
+    k_knn_backward_tree(TreeView t, const int32_t *__restrict__ slot_of, int64_t cap, int k,
+                        const int32_t *__restrict__ ids, const double *__restrict__ g,
+                        double *gs) {
+  __shared__ double acc[D][kBwdTile];
+  const int tid = threadIdx.x;
+  const int64_t t0 = (int64_t)blockIdx.x * kBwdTile;
+  const int64_t i = t0 + tid;
+#pragma unroll
+  for (int c = 0; c < D; ++c) acc[c][tid] = 0.0;
+  __syncthreads();
+  if (i < t.n) {
+    const int64_t r = t.id[i];
+    const double p[3] = {t.X[i], t.Y[i], D == 3 ? t.Z[i] : 0.0};
+    double own[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < k; ++j) {
+      const int32_t q = ids[r * k + j];
+      if (q < 0 || q >= cap) continue;
+      const int32_t sq = slot_of[q];
+      if (sq < 0 || sq >= t.n) continue;  // a dead id
+      const double w = g[r * k + j];
+      const double pq[3] = {t.X[sq], t.Y[sq], D == 3 ? t.Z[sq] : 0.0};
+      const int64_t ls = sq - t0;
+      const bool local = ls >= 0 && ls < kBwdTile;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double term = 2.0 * (p[c] - pq[c]) * w;
+        own[c] += term;
+        if (local) atomicAdd(&acc[c][ls], -term);
+        else unsafeAtomicAdd(&gs[c * t.n + sq], -term);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) atomicAdd(&acc[c][tid], own[c]);
+  }
+  __syncthreads();
+  if (i < t.n) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) unsafeAtomicAdd(&gs[c * t.n + i], acc[c][tid]);
+  }
+}
+
+template <int D>
+__global__ void k_unsort_grad(const int32_t *__restrict__ id, int64_t n,
+                              const double *__restrict__ gs, int64_t stride, double *grad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t r = id[i];
+#pragma unroll
+  for (int c = 0; c < D; ++c) grad[c * stride + r] = gs[c * n + i];
+}
+
+hipError_t knn_backward_tree(int dim, const TreeView &t, const int32_t *slot_of, int64_t cap,
+                             int k, const int32_t *ids, const double *g, double *grad,
+                             hipStream_t s) {
+  hipError_t e = fill_f64(grad, 0.0, (int64_t)dim * cap, s);
+  if (e != hipSuccess || t.n <= 0) return e;
+  double *gs = nullptr;
+  e = dev_alloc_n(&gs, (int64_t)dim * t.n, s);
+  if (e == hipSuccess) e = fill_f64(gs, 0.0, (int64_t)dim * t.n, s);
+  if (e == hipSuccess) {
+    const unsigned tiles = (unsigned)((t.n + kBwdTile - 1) / kBwdTile);
+    const unsigned grid = (unsigned)((t.n + 255) / 256);
+    if (dim == 3) {
+      k_knn_backward_tree<3><<<tiles, kBwdTile, 0, s>>>(t, slot_of, cap, k, ids, g, gs);
+      k_unsort_grad<3><<<grid, 256, 0, s>>>(t.id, t.n, gs, cap, grad);
+    } else {
+      k_knn_backward_tree<2><<<tiles, kBwdTile, 0, s>>>(t, slot_of, cap, k, ids, g, gs);
+      k_unsort_grad<2><<<grid, 256, 0, s>>>(t.id, t.n, gs, cap, grad);
+    }
+    e = hipGetLastError();
+  }
+  dev_release(gs, s);
+  return e;
+}
+
+}  // namespace zd
+

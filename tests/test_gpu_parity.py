@@ -302,6 +302,35 @@ def test_backward_modes_after_deletes():
     g.close()
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_backward_in_tree_order(dim):
+    """zd_knn_backward_tree (rows in the tree's Morton order, in-tile sums in
+    LDS) against the closed form and the id-order kernel, over several
+    1,024-point tiles, with dead rows after a streaming delete."""
+    n = 5000 if dim == 3 else 4000
+    P = W.uniform(n, dim, 412 + dim)
+    box = (np.zeros(dim), np.ones(dim))
+    g = zd.ZdTree(dev(P), 12, box=box)
+    g.delete(torch.arange(0, n, 7, dtype=torch.int32, device="cuda"))
+    assert g.pending() == (0, 0)
+    ids, d2 = g.knn(8)
+    idn = ids.cpu().numpy()
+    wn = np.where(idn >= 0, np.random.default_rng(414).uniform(0.5, 2, idn.shape), 0.0)
+    w = torch.from_numpy(wn).cuda()
+    ref = oracle.knn_grad(P, idn, wn)
+    got = g.knn_backward(ids, w).cpu().numpy().T
+    tol = 1e-13 * max(np.abs(ref).max(), 1.0)
+    assert np.abs(got - ref).max() <= tol
+    plain = zd.zd_knn_backward(dev(P), ids, w).cpu().numpy().T
+    assert np.abs(got - plain).max() <= tol
+    # in-place batches pending: the tree path refuses, autograd falls back
+    g.insert(dev(W.uniform(3, dim, 415) * 0.5 + 0.25))
+    assert g.pending()[0] > 0
+    with pytest.raises(zd.ZdError):
+        g.knn_backward(*g.knn(8))
+    g.close()
+
+
 @pytest.mark.parametrize("deterministic", [False, True])
 def test_autograd_function(deterministic):
     P = W.uniform(2000, 3, 410)
@@ -312,6 +341,15 @@ def test_autograd_function(deterministic):
     loss.backward()
     ref = oracle.knn_grad(P, ids.cpu().numpy(), np.ones((2000, 6)))
     assert np.allclose(xyz.grad.cpu().numpy().T, ref, rtol=1e-12, atol=1e-13)
+    # with an in-place batch pending the backward takes the id-order kernel
+    Q = W.uniform(5, 3, 411) * 0.5 + 0.25
+    g.insert(dev(Q))
+    P2 = np.concatenate([P, Q])
+    xyz2 = dev(P2).requires_grad_(True)
+    d2, ids = zd.knn_sq_dist(xyz2, g, 6, deterministic)
+    d2.sum().backward()
+    ref = oracle.knn_grad(P2, ids.cpu().numpy(), np.ones((2005, 6)))
+    assert np.allclose(xyz2.grad.cpu().numpy().T, ref, rtol=1e-12, atol=1e-13)
     g.close()
 
 
