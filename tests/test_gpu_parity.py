@@ -303,26 +303,39 @@ def test_backward_modes_after_deletes():
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-def test_backward_in_tree_order(dim):
+@pytest.mark.parametrize("dead", [False, True])
+def test_backward_in_tree_order(dim, dead):
     """zd_knn_backward_tree (rows in the tree's Morton order, in-tile sums in
     LDS) against the closed form and the id-order kernel, over several
-    1,024-point tiles, with dead rows after a streaming delete."""
+    1,024-point tiles: k = 8 and 12 (vector row loads; 12 with a half batch),
+    k = 13 (one scalar batch and a ragged one), rows read through an
+    unaligned view (scalar loads), with every id live or with dead rows
+    after a streaming delete."""
     n = 5000 if dim == 3 else 4000
     P = W.uniform(n, dim, 412 + dim)
     box = (np.zeros(dim), np.ones(dim))
     g = zd.ZdTree(dev(P), 12, box=box)
-    g.delete(torch.arange(0, n, 7, dtype=torch.int32, device="cuda"))
+    if dead:
+        g.delete(torch.arange(0, n, 7, dtype=torch.int32, device="cuda"))
     assert g.pending() == (0, 0)
-    ids, d2 = g.knn(8)
-    idn = ids.cpu().numpy()
-    wn = np.where(idn >= 0, np.random.default_rng(414).uniform(0.5, 2, idn.shape), 0.0)
-    w = torch.from_numpy(wn).cuda()
-    ref = oracle.knn_grad(P, idn, wn)
-    got = g.knn_backward(ids, w).cpu().numpy().T
-    tol = 1e-13 * max(np.abs(ref).max(), 1.0)
-    assert np.abs(got - ref).max() <= tol
-    plain = zd.zd_knn_backward(dev(P), ids, w).cpu().numpy().T
-    assert np.abs(got - plain).max() <= tol
+    rng = np.random.default_rng(414)
+    for k in (8, 12, 13):
+        ids, d2 = g.knn(k)
+        idn = ids.cpu().numpy()
+        wn = np.where(idn >= 0, rng.uniform(0.5, 2, idn.shape), 0.0)
+        ref = oracle.knn_grad(P, idn, wn)
+        tol = 1e-13 * max(np.abs(ref).max(), 1.0)
+        w = torch.from_numpy(wn).cuda()
+        # the same rows one element into a larger buffer: 8-byte aligned only
+        wbuf = torch.zeros(wn.size + 1, dtype=torch.float64, device="cuda")
+        wbuf[1:] = w.reshape(-1)
+        for ww in (w, wbuf[1:].view(n, k)):
+            got = g.knn_backward(ids, ww).cpu().numpy().T
+            assert np.abs(got - ref).max() <= tol, (k, ww.data_ptr() % 16)
+        plain = zd.zd_knn_backward(dev(P), ids, w).cpu().numpy().T
+        assert np.abs(got - plain).max() <= tol
+        if dead:
+            assert np.all(got[np.arange(0, n, 7)] == 0.0)
     # in-place batches pending: the tree path refuses, autograd falls back
     g.insert(dev(W.uniform(3, dim, 415) * 0.5 + 0.25))
     assert g.pending()[0] > 0
