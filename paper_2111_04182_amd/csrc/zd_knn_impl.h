@@ -26,12 +26,16 @@
 //     the 32 sorted positions on either side (its Morton neighbours), which
 //     tightens every lane's k-th distance before the walk starts; those
 //     positions are skipped later.
+// For all-points rows at k > 16 four lanes share one query (TeamSet): a
+// wavefront then answers its 64 positions as four groups of 16, one shared
+// walk each.
 #pragma once
 
 #include "zd_internal.h"
 #include "zd_sortnet.h"
 
 #include <climits>
+#include <type_traits>
 #include <utility>
 
 namespace zd {
@@ -229,7 +233,8 @@ struct Heap {
   }
 };
 
-// For k > 50 (up to 100, the largest k of the paper's sweep) the candidate
+// For external and root-based queries with k > 50 (up to 100, the largest
+// k of the paper's sweep; the all-points rows use TeamSet) the candidate
 // set is a binary max-heap of the k best (d2, id) per lane, kept in LDS
 // (slot-major: slot s of lane l at [s * 64 + l], so a lane's bank never
 // depends on the slot it touches): the heap the paper switches to for large
@@ -315,7 +320,8 @@ struct LdsHeap {
   }
 };
 
-// For k in (24, 50] the k best are split: the lower M = K - R slots,
+// For external and root-based queries with k in (24, 50] the k best are
+// split: the lower M = K - R slots,
 // sorted, in LDS (slot-major like the heap above), the upper R slots in
 // registers with the segmented shift.  Entries mostly land near the k-th
 // slot, so most insertions stay in registers; one that reaches below them
@@ -445,6 +451,126 @@ struct SplitSet {
   }
 };
 
+// Moves within each group of four lanes (DPP quad permutations; every lane
+// of the wavefront is active wherever these run).
+template <int R>
+__device__ __forceinline__ int32_t quad_bcast(int32_t v) {
+  return __builtin_amdgcn_mov_dpp(v, R | (R << 2) | (R << 4) | (R << 6), 0xf, 0xf, false);
+}
+template <int R>
+__device__ __forceinline__ double quad_bcast(double v) {
+  const int64_t b = __double_as_longlong(v);
+  const int32_t lo = quad_bcast<R>((int32_t)b), hi = quad_bcast<R>((int32_t)(b >> 32));
+  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+// lane i of each four takes lane i - 1's value (lane 0 keeps its own)
+__device__ __forceinline__ int32_t quad_prev(int32_t v) {
+  return __builtin_amdgcn_mov_dpp(v, 0 | (0 << 2) | (1 << 4) | (2 << 6), 0xf, 0xf, false);
+}
+__device__ __forceinline__ double quad_prev(double v) {
+  const int64_t b = __double_as_longlong(v);
+  const int32_t lo = quad_prev((int32_t)b), hi = quad_prev((int32_t)(b >> 32));
+  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+// For the all-points rows at large k, four lanes (a team) answer one query,
+// so a wavefront answers 16, and hold its candidate set together: team lane
+// `sub` holds the sorted slots [S sub, S sub + S), S = ceil(K / 4), the k
+// best in the last k of the 4S slots as in Heap.  Each lane scores a quarter
+// of every list of points, and the team takes its four lanes' candidates
+// one after the other: every lane of the team compares the candidate with
+// its S slots and shifts them, the lowest slot taking the previous lane's
+// old last entry across the lane boundary.  One insertion costs O(k / 4)
+// per lane instead of the O(k) shift of one lane's whole set, all 16 teams
+// insert at once, and the registers hold a quarter of the set; the
+// wavefront's shared walk covers 16 queries' balls instead of 64.
+template <int K>
+struct TeamSet {
+  static constexpr int T = 4;
+  static constexpr int S = (K + T - 1) / T;
+  static constexpr int KT = S * T;
+  double d[S];
+  int32_t id[S];
+  double kd;  // the team's k-th entry (slot KT - 1, held by team lane 3)
+  int32_t ki;
+  int sub;
+
+  __device__ __forceinline__ void init(int k, bool live) {
+    sub = threadIdx.x & (T - 1);
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const bool used = live && sub * S + j >= KT - k;
+      d[j] = used ? INFINITY : -INFINITY;
+      id[j] = used ? INT_MAX : INT_MIN;
+    }
+    kd = live ? INFINITY : -INFINITY;
+    ki = live ? INT_MAX : INT_MIN;
+  }
+
+  __device__ __forceinline__ double kth() const { return kd; }
+
+  // team lane R's candidate, offered to the whole team
+  template <int R>
+  __device__ __forceinline__ void take(double dd, int32_t q) {
+    const double cd = quad_bcast<R>(dd);
+    const int32_t cq = quad_bcast<R>(q);
+    const bool cw = cand_lt(cd, cq, kd, ki);
+    if (__ballot(cw) == 0) return;
+    // slot by slot from the top, with only the masks of two neighbouring
+    // slots live (an array of S lane masks would crowd the scalar registers):
+    // slot j takes slot j-1's entry if the candidate precedes that entry,
+    // else the candidate if it precedes slot j, else keeps its own
+    bool hi = cw & cand_lt(cd, cq, d[S - 1], id[S - 1]);
+    // the previous lane's last slot, and whether the candidate precedes it
+    // (the moves run on every lane: a lane left out of a DPP move is left
+    // out as its source too)
+    const double pd = quad_prev(d[S - 1]);
+    const int32_t pi = quad_prev(id[S - 1]);
+    const int32_t pl = quad_prev((int32_t)hi);
+    const bool plt = (pl != 0) & (sub > 0);
+#pragma unroll
+    for (int j = S - 1; j > 0; --j) {
+      const bool lo = cw & cand_lt(cd, cq, d[j - 1], id[j - 1]);
+      const double nd = lo ? d[j - 1] : (hi ? cd : d[j]);
+      const int32_t ni = lo ? id[j - 1] : (hi ? cq : id[j]);
+      d[j] = nd;
+      id[j] = ni;
+      hi = lo;
+    }
+    const double nd = plt ? pd : (hi ? cd : d[0]);
+    const int32_t ni = plt ? pi : (hi ? cq : id[0]);
+    d[0] = nd;
+    id[0] = ni;
+    kd = quad_bcast<T - 1>(d[S - 1]);
+    ki = quad_bcast<T - 1>(id[S - 1]);
+  }
+
+  // every lane offers one candidate (+inf, INT_MAX for none); a team
+  // inserts its lanes' candidates in lane order, each tested against the
+  // k-th entry as it stands after the ones before
+  __device__ __forceinline__ void offer_team(double dd, int32_t q) {
+    const bool w = dd <= kd;
+    if (__ballot(w) == 0) return;
+    take<0>(dd, q);
+    take<1>(dd, q);
+    take<2>(dd, q);
+    take<3>(dd, q);
+  }
+
+  // each lane writes its slots' part of the row
+  __device__ __forceinline__ void write(int k, int32_t *out_ids, double *out_d2) const {
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const int g = sub * S + j;
+      if (g >= KT - k) {
+        const int o = g - (KT - k);
+        out_ids[o] = id[j] == INT_MAX ? -1 : id[j];
+        out_d2[o] = d[j];
+      }
+    }
+  }
+};
+
 // Per k bucket: the candidate set, its per-lane LDS slots, whether the
 // prescore runs in the shared order over a 64-entry stage (the LDS heap)
 // or each lane's near-first order over the whole window, and whether the
@@ -524,8 +650,9 @@ struct Cand {
 };
 
 // The per-lane state of one wavefront's shared search.
-template <int D, int K, bool kExt = false, bool kPool = false>
+template <int D, int K, bool kExt = false, bool kPool = false, bool kTeam = false>
 struct WaveSearch {
+  static_assert(!(kTeam && kExt), "lane teams serve the all-points rows only");
   const TreeView &t;
   Cand *stage;                   // this wavefront's 64-entry LDS slice (candidates)
   double px, py, pz;             // this lane's query
@@ -537,7 +664,7 @@ struct WaveSearch {
   int64_t budget;                // walk bound (never reached on a valid tree)
   bool gave_up = false;          // the walk stopped before it finished
   uint64_t key_ref;              // Morton key of the group's middle query (child order)
-  typename HeapFor<K>::type h;
+  std::conditional_t<kTeam, TeamSet<K>, typename HeapFor<K>::type> h;
   __device__ __forceinline__ WaveSearch(const TreeView &t_, Cand *stage_) : t(t_), stage(stage_) {}
 
   __device__ __forceinline__ bool wants(const double *lo, const double *hi) const {
@@ -644,11 +771,101 @@ struct WaveSearch {
     skip_hi = uni((int32_t)b);
   }
 
+  // prescore_near_first for lane teams: the team's four lanes take the
+  // steps of its query's near-first order in turns (lane `sub` takes steps
+  // 1 + sub, 5 + sub, ...), each round offering four candidates to the team.
+  __device__ __forceinline__ void prescore_team(int64_t a, int64_t b, int64_t own) {
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & 3;
+    const int cnt = (int)(b - a + 1);  // <= 16 + 2 prescore_reach<K>() entries of the stage
+    for (int j = lane; j < cnt; j += 64) {
+      Cand q;
+      q.x = t.X[a + j];
+      q.y = t.Y[a + j];
+      q.z = D == 3 ? t.Z[a + j] : 0.0;
+      q.id = t.id[a + j];
+      q.pad = 0;
+      stage[j] = q;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int o = valid ? (int)(own - a) : 0;
+    for (int s0 = 1; s0 < cnt; s0 += 4) {
+      const int s = s0 + sub;
+      const int m = (s + 1) >> 1;
+      int j = (s & 1) ? o + m : o - m;
+      j = j >= cnt ? j - cnt : (j < 0 ? j + cnt : j);
+      const bool in = s < cnt;
+      const Cand q = stage[in ? j : 0];
+      const double dd = dist2<D>(px, py, pz, q.x, q.y, q.z);
+      h.offer_team(in ? dd : INFINITY, in ? q.id : INT_MAX);
+    }
+    __builtin_amdgcn_wave_barrier();
+    skip_lo = uni((int32_t)a);
+    skip_hi = uni((int32_t)b);
+  }
+
+  // scan_leaf for lane teams: the team's lanes score every fourth point of
+  // each staged chunk and the team takes them four at a time
+  __device__ __forceinline__ void scan_leaf_team(int32_t leaf) {
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & 3;
+    const int32_t b = uni(t.leaf_begin[leaf]), e = uni(t.leaf_begin[leaf + 1]);
+    int32_t pn = 0, pb = 0;
+    if constexpr (kPool) {
+      pn = uni(t.ovf_cnt[leaf]);
+      pb = pn > 0 ? uni(t.ovf_blk[leaf]) * kOvfBlock : 0;
+    }
+    const int32_t ev = e + pn;
+    const int32_t skip_end = kPool ? min(skip_hi + 1, e) : skip_hi + 1;
+    for (int32_t c = b; c < ev; c += 64) {
+      const int32_t j = c + lane;
+      if (j < e) {
+        Cand q;
+        q.x = t.X[j];
+        q.y = t.Y[j];
+        q.z = D == 3 ? t.Z[j] : 0.0;
+        q.id = t.id[j];
+        q.pad = 0;
+        stage[lane] = q;
+      } else if (kPool && j < ev) {
+        const int32_t x = pb + (j - e);
+        Cand q;
+        q.x = t.pX[x];
+        q.y = t.pY[x];
+        q.z = D == 3 ? t.pZ[x] : 0.0;
+        q.id = t.pid[x];
+        q.pad = 0;
+        stage[lane] = q;
+      }
+      __builtin_amdgcn_wave_barrier();
+      const int32_t cnt = min(64, ev - c);
+      // skipped local range [sa, sb) (empty when sa >= sb)
+      const int32_t sa = max(skip_lo - c, 0);
+      const int32_t sb = min(skip_end - c, cnt);
+      for (int32_t j0 = 0; j0 < cnt; j0 += 4) {
+        if (j0 >= sa && j0 + 4 <= sb) continue;  // four skipped points
+        const int32_t jj = j0 + sub;
+        const bool in = jj < cnt && !(jj >= sa && jj < sb);
+        const Cand q = stage[in ? jj : 0];
+        const double dd = dist2<D>(px, py, pz, q.x, q.y, q.z);
+        h.offer_team(in ? dd : INFINITY, in ? q.id : INT_MAX);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+
   // every lane scores every point of the leaf, except the sorted positions
   // [skip_lo, skip_hi] already scored by all lanes (for all-points rows they
   // hold every lane's own point, so no self test is needed here) and, for
   // external queries, the lane's own leaf
   __device__ __forceinline__ void scan_leaf(int32_t leaf) {
+    if constexpr (kTeam)
+      scan_leaf_team(leaf);
+    else
+      scan_leaf_lanes(leaf);
+  }
+
+  __device__ __forceinline__ void scan_leaf_lanes(int32_t leaf) {
     const int lane = threadIdx.x & 63;
     const int32_t b = uni(t.leaf_begin[leaf]), e = uni(t.leaf_begin[leaf + 1]);
     // points placed in this leaf by small inserts follow as virtual
@@ -817,22 +1034,38 @@ constexpr size_t wave_lds_bytes() {
          (size_t)HeapFor<K>::lds_slots * 64 * (sizeof(double) + sizeof(int32_t));
 }
 
+// All-points rows in lane teams (TeamSet) for these buckets; their LDS is
+// the candidate stage only.  10M uniform points, rows identical: k = 20 /
+// 24 / 32 / 40 / 50 / 64 / 100 in 24.3 / 29.8 / 36.0 / 53.1 / 67.3 / 112 /
+// 336 ms against 26.3 / 32.8 / 49.2 / 76.4 / 101.6 / 231 / 489 ms with a
+// set per lane (before the register caps below); k = 16 slower in teams
+// (21.7 against 17.6 ms).
+template <int K>
+constexpr bool all_team() {
+  return K >= 20;
+}
+template <int K>
+constexpr size_t all_lds_bytes() {
+  return all_team<K>() ? (64 + 2 * prescore_reach<K>()) * sizeof(Cand) : wave_lds_bytes<K>();
+}
+
 // Wavefronts per workgroup of a query launch: the requested 1, 2 or 4,
 // halved while the workgroup's LDS would exceed one CU's 160 KiB (only the
 // k > 32 buckets, whose candidate sets live wholly or partly in LDS, come
 // near it).
-template <int K>
+template <int K, bool kAll = false>
 int fit_waves(int want) {
+  const size_t per = kAll ? all_lds_bytes<K>() : wave_lds_bytes<K>();
   int w = want == 2 || want == 4 ? want : 1;
-  while (w > 1 && (size_t)w * wave_lds_bytes<K>() > 160 * 1024) w >>= 1;
+  while (w > 1 && (size_t)w * per > 160 * 1024) w >>= 1;
   return w;
 }
 
-template <int D, int K, bool E, bool P>
-__device__ __forceinline__ void bind_lds(WaveSearch<D, K, E, P> &s, char *smem, int w) {
-  char *base = smem + (size_t)w * wave_lds_bytes<K>();
+template <int D, int K, bool E, bool P, bool TM>
+__device__ __forceinline__ void bind_lds(WaveSearch<D, K, E, P, TM> &s, char *smem, int w) {
+  char *base = smem + (size_t)w * (TM ? all_lds_bytes<K>() : wave_lds_bytes<K>());
   s.stage = reinterpret_cast<Cand *>(base);
-  if constexpr (HeapFor<K>::lds_slots > 0) {
+  if constexpr (!TM && HeapFor<K>::lds_slots > 0) {
     constexpr int kStage = HeapFor<K>::shared_prescore ? 64 : 64 + 2 * prescore_reach<K>();
     double *hd = reinterpret_cast<double *>(base + kStage * sizeof(Cand));
     s.h.bind(hd, reinterpret_cast<int32_t *>(hd + (size_t)HeapFor<K>::lds_slots * 64));
@@ -843,23 +1076,29 @@ __device__ __forceinline__ void bind_lds(WaveSearch<D, K, E, P> &s, char *smem, 
 // (5 wavefronts per SIMD); capped at 80 it keeps 6 resident and spills 7
 // dwords to scratch (reloaded once per node or leaf step, never inside the
 // insertion), which measured 3-4% faster.  At k = 12, 98 VGPRs (4 per SIMD)
-// capped at 96 gives 5 and measured 7% faster.  At k = 24, 172 VGPRs (2 per
-// SIMD) capped at 168 gives 3 and measured 20% faster; k = 20 keeps 3 per
-// SIMD; k = 32 (split set, 24 register slots) capped at 168 measured 10%
-// faster.  Other buckets keep the compiler's choice (caps that spill inside
-// the insertion, k = 12 at 80, k = 16 at 96, k = 32 all in registers at
-// 168, run up to twice as long).
+// capped at 96 gives 5 and measured 7% faster.  The lane-team buckets
+// (k >= 17) trade a few spilled dwords for occupancy, 10M uniform points:
+// k = 20 at 80 VGPRs (6 per SIMD) 24.3 -> 23.4 ms, k = 24, 32 and 40 at 96
+// (5) 29.8 -> 27.3, 36.0 -> 33.9 and 53.1 -> 45.2 ms, k = 50 and 64 at 128
+// (4) 67.3 -> 60.2 and 111.9 -> 83.4 ms, k = 100 at 256 (2) 336 -> 194 ms
+// (at 168, 173 spilled dwords: 209 ms).  Other buckets keep the compiler's
+// choice (caps that spill inside the insertion, k = 12 at 80 or k = 16 at
+// 96, run up to twice as long).
 template <int K>
 constexpr int knn_all_min_waves() {
-  return K == 10 ? 6 : (K == 12 ? 5 : (K == 20 || K == 24 || K == 32 ? 3 : 1));
+  return K == 10 || K == 20 ? 6
+         : K == 12 || K == 24 || K == 32 || K == 40 ? 5
+         : K == 50 || K == 64 ? 4
+         : K == 100 ? 2
+                    : 1;
 }
 
-// One wavefront answers the all-points rows of sorted positions [g0, last]
-// (at most 64), which lie in the cloud [c_lo, c_hi] (the whole tree for a
-// single tree).  `smem` is the workgroup's dynamic LDS, w the wavefront's
+// The all-points rows of sorted positions [g0, last] (at most 64), which
+// lie in the cloud [c_lo, c_hi] (the whole tree for a single tree), one
+// query per lane.  `smem` is the workgroup's dynamic LDS, w the wavefront's
 // index in the workgroup.
 template <int D, int K, bool kPool>
-__device__ __forceinline__ void all_points_group(const TreeView &t, int k,
+__device__ __forceinline__ void all_points_lanes(const TreeView &t, int k,
                                                  int32_t *__restrict__ out_ids,
                                                  double *__restrict__ out_d2, int64_t g0,
                                                  int64_t last, int64_t c_lo, int64_t c_hi,
@@ -904,6 +1143,64 @@ __device__ __forceinline__ void all_points_group(const TreeView &t, int k,
   s.run_from(G);
   s.report();
   if (s.valid) s.h.write(k, out_ids + (int64_t)s.self * k, out_d2 + (int64_t)s.self * k);
+}
+
+// The same rows in lane teams (TeamSet): sorted positions [g0, last], at
+// most 16, one query per four lanes.
+template <int D, int K, bool kPool>
+__device__ __forceinline__ void all_points_team(const TreeView &t, int k,
+                                                int32_t *__restrict__ out_ids,
+                                                double *__restrict__ out_d2, int64_t g0,
+                                                int64_t last, int64_t c_lo, int64_t c_hi,
+                                                char *smem, int w) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = min(g0 + (lane >> 2), last);
+  WaveSearch<D, K, false, kPool, true> s(t, nullptr);
+  bind_lds(s, smem, w);
+  s.px = t.X[i];
+  s.py = t.Y[i];
+  s.pz = D == 3 ? t.Z[i] : 0.0;
+  s.valid = g0 + (lane >> 2) <= last && !isnan(s.px);
+  s.self = t.id[i];
+  const int mid = (int)((last - g0) / 2);
+  s.budget = t.walk_limit > 0 ? t.walk_limit : 4 * t.n + 256;
+  s.key_ref = uni((int32_t)(t.key[g0 + mid] >> 32));
+  s.key_ref = (s.key_ref << 32) | (uint32_t)uni((int32_t)t.key[g0 + mid]);
+  s.h.init(k, s.valid);
+  s.prescore_team(max(c_lo, g0 - prescore_reach<K>()), min(c_hi, last + prescore_reach<K>()), i);
+  const int32_t lf = uni(t.leaf_of[g0]), ll = uni(t.leaf_of[last]);
+  int32_t G = ~lf;
+  if (lf != ll) {
+    int32_t x = uni(t.leaf_parent[lf]) >> 1;
+    for (int guard = 0; guard < 130 && uni(t.inode[x].last_leaf) < ll; ++guard) {
+      const int32_t par = uni(t.inode[x].parent);
+      if (par < 0) break;
+      x = par >> 1;
+    }
+    G = x;
+  }
+  s.run_from(G);
+  s.report();
+  if (s.valid) s.h.write(k, out_ids + (int64_t)s.self * k, out_d2 + (int64_t)s.self * k);
+}
+
+// One wavefront answers the all-points rows of sorted positions [g0, last]
+// (at most 64) of the cloud [c_lo, c_hi]: in one group of 64 lanes, or,
+// for the team buckets, in up to four groups of 16 queries one after the
+// other.
+template <int D, int K, bool kPool>
+__device__ __forceinline__ void all_points_group(const TreeView &t, int k,
+                                                 int32_t *__restrict__ out_ids,
+                                                 double *__restrict__ out_d2, int64_t g0,
+                                                 int64_t last, int64_t c_lo, int64_t c_hi,
+                                                 char *smem, int w) {
+  if constexpr (all_team<K>()) {
+    for (int64_t sg = g0; sg <= last; sg += 16)
+      all_points_team<D, K, kPool>(t, k, out_ids, out_d2, sg, min(sg + 15, last), c_lo, c_hi,
+                                   smem, w);
+  } else {
+    all_points_lanes<D, K, kPool>(t, k, out_ids, out_d2, g0, last, c_lo, c_hi, smem, w);
+  }
 }
 
 template <int D, int K, bool kPool>
@@ -1115,14 +1412,14 @@ template <int D, int K>
 hipError_t launch_knn_all(const TreeView &t, int k, int32_t *ids, double *d2, hipStream_t s,
                           const int4 *groups, int64_t ngroups, int query_waves) {
   const int64_t waves = groups ? ngroups : (t.n + 63) / 64;
-  const int wpb = fit_waves<K>(query_waves);
+  const int wpb = fit_waves<K, true>(query_waves);
   const dim3 grid((unsigned)((waves + wpb - 1) / wpb)), block(64 * wpb);
   if (t.ovf_cnt)
-    k_knn_all<D, K, true><<<grid, block, wpb * wave_lds_bytes<K>(), s>>>(t, k, ids, d2, groups,
-                                                                         ngroups);
+    k_knn_all<D, K, true><<<grid, block, wpb * all_lds_bytes<K>(), s>>>(t, k, ids, d2, groups,
+                                                                        ngroups);
   else
-    k_knn_all<D, K, false><<<grid, block, wpb * wave_lds_bytes<K>(), s>>>(t, k, ids, d2, groups,
-                                                                          ngroups);
+    k_knn_all<D, K, false><<<grid, block, wpb * all_lds_bytes<K>(), s>>>(t, k, ids, d2, groups,
+                                                                         ngroups);
   return hipGetLastError();
 }
 

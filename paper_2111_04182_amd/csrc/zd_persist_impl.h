@@ -401,7 +401,7 @@ __device__ void p_build_cloud(PBuildLds &S, const PersistArgs &a, const PersistT
 
 template <int K>
 constexpr size_t persist_lds_bytes(int waves) {
-  const size_t q = (size_t)waves * wave_lds_bytes<K>();
+  const size_t q = (size_t)waves * all_lds_bytes<K>();
   return q > sizeof(PBuildLds) ? q : sizeof(PBuildLds);
 }
 
@@ -478,7 +478,7 @@ __global__ void __launch_bounds__(kPThreads)
 template <int D, int K>
 hipError_t launch_forest_persistent(const PersistArgs &a, const PersistTree &pt,
                                     const TreeView &t, hipStream_t s) {
-  const int qw = fit_waves<K>(kPWaves);
+  const int qw = fit_waves<K, true>(kPWaves);
   const size_t lds = persist_lds_bytes<K>(qw);
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);

@@ -53,7 +53,7 @@ def check_rows(t, allp, live, k, Q, what):
     assert np.array_equal(o_ids.cpu().numpy(), want[0]), what + " noalloc"
 
 
-@pytest.mark.parametrize("dim,L,k", [(3, 16, 10), (2, 8, 5), (3, 24, 70)])
+@pytest.mark.parametrize("dim,L,k", [(3, 16, 10), (2, 8, 5), (3, 24, 70), (2, 12, 33)])
 def test_small_batches_in_place(dim, L, k):
     rng = np.random.default_rng(200 + dim + L)
     box = (np.zeros(dim), np.ones(dim))
