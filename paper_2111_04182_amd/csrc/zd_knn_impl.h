@@ -26,9 +26,9 @@
 //     the 32 sorted positions on either side (its Morton neighbours), which
 //     tightens every lane's k-th distance before the walk starts; those
 //     positions are skipped later.
-// For all-points rows at k > 16 four lanes share one query (TeamSet): a
-// wavefront then answers its 64 positions as four groups of 16, one shared
-// walk each.
+// For all-points rows at k > 16 a team of 4 or 8 lanes shares one query
+// (TeamSet): a wavefront then answers its 64 positions as groups of 16 or
+// 8 queries, one shared walk each.
 #pragma once
 
 #include "zd_internal.h"
@@ -451,47 +451,59 @@ struct SplitSet {
   }
 };
 
-// Moves within each group of four lanes (DPP quad permutations; every lane
-// of the wavefront is active wherever these run).
-template <int R>
-__device__ __forceinline__ int32_t quad_bcast(int32_t v) {
-  return __builtin_amdgcn_mov_dpp(v, R | (R << 2) | (R << 4) | (R << 6), 0xf, 0xf, false);
+// Moves within each team of T = 4 or 8 consecutive lanes (every lane of the
+// wavefront is active wherever these run).  T = 4: DPP quad permutations;
+// T = 8: a swizzle that reads lane (l & ~7) | R, and a DPP row shift by one.
+template <int T, int R>
+__device__ __forceinline__ int32_t team_bcast(int32_t v) {
+  static_assert(T == 4 || T == 8, "teams of 4 or 8 lanes");
+  if constexpr (T == 4)
+    return __builtin_amdgcn_mov_dpp(v, R | (R << 2) | (R << 4) | (R << 6), 0xf, 0xf, false);
+  else
+    return __builtin_amdgcn_ds_swizzle(v, (R << 5) | 0x18);
 }
-template <int R>
-__device__ __forceinline__ double quad_bcast(double v) {
+template <int T, int R>
+__device__ __forceinline__ double team_bcast(double v) {
   const int64_t b = __double_as_longlong(v);
-  const int32_t lo = quad_bcast<R>((int32_t)b), hi = quad_bcast<R>((int32_t)(b >> 32));
+  const int32_t lo = team_bcast<T, R>((int32_t)b), hi = team_bcast<T, R>((int32_t)(b >> 32));
   return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
 }
-// lane i of each four takes lane i - 1's value (lane 0 keeps its own)
-__device__ __forceinline__ int32_t quad_prev(int32_t v) {
-  return __builtin_amdgcn_mov_dpp(v, 0 | (0 << 2) | (1 << 4) | (2 << 6), 0xf, 0xf, false);
+// lane i of each team takes lane i - 1's value (the team's first lane gets
+// some other value, which the caller ignores)
+template <int T>
+__device__ __forceinline__ int32_t team_prev(int32_t v) {
+  if constexpr (T == 4)
+    return __builtin_amdgcn_mov_dpp(v, 0 | (0 << 2) | (1 << 4) | (2 << 6), 0xf, 0xf, false);
+  else
+    return __builtin_amdgcn_update_dpp(v, v, 0x111, 0xf, 0xf, false);  // row_shr:1
 }
-__device__ __forceinline__ double quad_prev(double v) {
+template <int T>
+__device__ __forceinline__ double team_prev(double v) {
   const int64_t b = __double_as_longlong(v);
-  const int32_t lo = quad_prev((int32_t)b), hi = quad_prev((int32_t)(b >> 32));
+  const int32_t lo = team_prev<T>((int32_t)b), hi = team_prev<T>((int32_t)(b >> 32));
   return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
 }
 
-// For the all-points rows at large k, four lanes (a team) answer one query,
-// so a wavefront answers 16, and hold its candidate set together: team lane
-// `sub` holds the sorted slots [S sub, S sub + S), S = ceil(K / 4), the k
-// best in the last k of the 4S slots as in Heap.  Each lane scores a quarter
-// of every list of points, and the team takes its four lanes' candidates
-// one after the other: every lane of the team compares the candidate with
-// its S slots and shifts them, the lowest slot taking the previous lane's
-// old last entry across the lane boundary.  One insertion costs O(k / 4)
-// per lane instead of the O(k) shift of one lane's whole set, all 16 teams
-// insert at once, and the registers hold a quarter of the set; the
-// wavefront's shared walk covers 16 queries' balls instead of 64.
-template <int K>
+// For the all-points rows at large k, T = 4 or 8 lanes (a team) answer one
+// query, so a wavefront answers 64 / T, and hold its candidate set
+// together: team lane `sub` holds the sorted slots [S sub, S sub + S),
+// S = ceil(K / T), the k best in the last k of the T S slots as in Heap.
+// Each lane scores every T-th point of every list of points, and the team
+// takes its lanes' candidates one after the other: every lane of the team
+// compares the candidate with its S slots and shifts them, the lowest slot
+// taking the previous lane's old last entry across the lane boundary.  One
+// insertion costs O(k / T) per lane instead of the O(k) shift of one lane's
+// whole set, all teams insert at once, and the registers hold 1/T of the
+// set; the wavefront's shared walk covers 64 / T queries' balls instead of
+// 64.
+template <int K, int T_>
 struct TeamSet {
-  static constexpr int T = 4;
+  static constexpr int T = T_;
   static constexpr int S = (K + T - 1) / T;
   static constexpr int KT = S * T;
   double d[S];
   int32_t id[S];
-  double kd;  // the team's k-th entry (slot KT - 1, held by team lane 3)
+  double kd;  // the team's k-th entry (slot KT - 1, held by team lane T - 1)
   int32_t ki;
   int sub;
 
@@ -512,8 +524,8 @@ struct TeamSet {
   // team lane R's candidate, offered to the whole team
   template <int R>
   __device__ __forceinline__ void take(double dd, int32_t q) {
-    const double cd = quad_bcast<R>(dd);
-    const int32_t cq = quad_bcast<R>(q);
+    const double cd = team_bcast<T, R>(dd);
+    const int32_t cq = team_bcast<T, R>(q);
     const bool cw = cand_lt(cd, cq, kd, ki);
     if (__ballot(cw) == 0) return;
     // slot by slot from the top, with only the masks of two neighbouring
@@ -524,9 +536,9 @@ struct TeamSet {
     // the previous lane's last slot, and whether the candidate precedes it
     // (the moves run on every lane: a lane left out of a DPP move is left
     // out as its source too)
-    const double pd = quad_prev(d[S - 1]);
-    const int32_t pi = quad_prev(id[S - 1]);
-    const int32_t pl = quad_prev((int32_t)hi);
+    const double pd = team_prev<T>(d[S - 1]);
+    const int32_t pi = team_prev<T>(id[S - 1]);
+    const int32_t pl = team_prev<T>((int32_t)hi);
     const bool plt = (pl != 0) & (sub > 0);
 #pragma unroll
     for (int j = S - 1; j > 0; --j) {
@@ -541,8 +553,8 @@ struct TeamSet {
     const int32_t ni = plt ? pi : (hi ? cq : id[0]);
     d[0] = nd;
     id[0] = ni;
-    kd = quad_bcast<T - 1>(d[S - 1]);
-    ki = quad_bcast<T - 1>(id[S - 1]);
+    kd = team_bcast<T, T - 1>(d[S - 1]);
+    ki = team_bcast<T, T - 1>(id[S - 1]);
   }
 
   // every lane offers one candidate (+inf, INT_MAX for none); a team
@@ -551,10 +563,11 @@ struct TeamSet {
   __device__ __forceinline__ void offer_team(double dd, int32_t q) {
     const bool w = dd <= kd;
     if (__ballot(w) == 0) return;
-    take<0>(dd, q);
-    take<1>(dd, q);
-    take<2>(dd, q);
-    take<3>(dd, q);
+    take_all(dd, q, std::make_integer_sequence<int, T>{});
+  }
+  template <int... R>
+  __device__ __forceinline__ void take_all(double dd, int32_t q, std::integer_sequence<int, R...>) {
+    (take<R>(dd, q), ...);
   }
 
   // each lane writes its slots' part of the row
@@ -570,6 +583,17 @@ struct TeamSet {
     }
   }
 };
+
+// Lanes per query of the all-points rows, per k bucket (0: one lane per
+// query).  10M points, rows identical: teams of 8 at k = 64 and 100 took
+// 75.7 and 138.6 ms on uniform points (62.6 and 116.7 on sphere surfaces)
+// against 83.3 and 192.8 (71.6 and 156.7) for teams of 4, whose 25 slots
+// per lane at k = 100 left one wavefront per SIMD; at k = 50 the two sizes
+// split (uniform 62.7 against 60.2 ms, spheres 50.8 against 53.4).
+template <int K>
+constexpr int team_size() {
+  return K > 50 ? 8 : (K > 16 ? 4 : 0);
+}
 
 // Per k bucket: the candidate set, its per-lane LDS slots, whether the
 // prescore runs in the shared order over a 64-entry stage (the LDS heap)
@@ -664,7 +688,8 @@ struct WaveSearch {
   int64_t budget;                // walk bound (never reached on a valid tree)
   bool gave_up = false;          // the walk stopped before it finished
   uint64_t key_ref;              // Morton key of the group's middle query (child order)
-  std::conditional_t<kTeam, TeamSet<K>, typename HeapFor<K>::type> h;
+  static constexpr int kT = team_size<K>() > 0 ? team_size<K>() : 4;  // lanes per query in teams
+  std::conditional_t<kTeam, TeamSet<K, kT>, typename HeapFor<K>::type> h;
   __device__ __forceinline__ WaveSearch(const TreeView &t_, Cand *stage_) : t(t_), stage(stage_) {}
 
   __device__ __forceinline__ bool wants(const double *lo, const double *hi) const {
@@ -771,13 +796,14 @@ struct WaveSearch {
     skip_hi = uni((int32_t)b);
   }
 
-  // prescore_near_first for lane teams: the team's four lanes take the
-  // steps of its query's near-first order in turns (lane `sub` takes steps
-  // 1 + sub, 5 + sub, ...), each round offering four candidates to the team.
+  // prescore_near_first for lane teams: the team's kT lanes take the steps
+  // of its query's near-first order in turns (lane `sub` takes steps
+  // 1 + sub, 1 + kT + sub, ...), each round offering kT candidates to the
+  // team.
   __device__ __forceinline__ void prescore_team(int64_t a, int64_t b, int64_t own) {
     const int lane = threadIdx.x & 63;
-    const int sub = lane & 3;
-    const int cnt = (int)(b - a + 1);  // <= 16 + 2 prescore_reach<K>() entries of the stage
+    const int sub = lane & (kT - 1);
+    const int cnt = (int)(b - a + 1);  // <= 64 / kT + 2 prescore_reach<K>() entries of the stage
     for (int j = lane; j < cnt; j += 64) {
       Cand q;
       q.x = t.X[a + j];
@@ -789,7 +815,7 @@ struct WaveSearch {
     }
     __builtin_amdgcn_wave_barrier();
     const int o = valid ? (int)(own - a) : 0;
-    for (int s0 = 1; s0 < cnt; s0 += 4) {
+    for (int s0 = 1; s0 < cnt; s0 += kT) {
       const int s = s0 + sub;
       const int m = (s + 1) >> 1;
       int j = (s & 1) ? o + m : o - m;
@@ -804,11 +830,11 @@ struct WaveSearch {
     skip_hi = uni((int32_t)b);
   }
 
-  // scan_leaf for lane teams: the team's lanes score every fourth point of
-  // each staged chunk and the team takes them four at a time
+  // scan_leaf for lane teams: the team's lanes score every kT-th point of
+  // each staged chunk and the team takes them kT at a time
   __device__ __forceinline__ void scan_leaf_team(int32_t leaf) {
     const int lane = threadIdx.x & 63;
-    const int sub = lane & 3;
+    const int sub = lane & (kT - 1);
     const int32_t b = uni(t.leaf_begin[leaf]), e = uni(t.leaf_begin[leaf + 1]);
     int32_t pn = 0, pb = 0;
     if constexpr (kPool) {
@@ -842,8 +868,8 @@ struct WaveSearch {
       // skipped local range [sa, sb) (empty when sa >= sb)
       const int32_t sa = max(skip_lo - c, 0);
       const int32_t sb = min(skip_end - c, cnt);
-      for (int32_t j0 = 0; j0 < cnt; j0 += 4) {
-        if (j0 >= sa && j0 + 4 <= sb) continue;  // four skipped points
+      for (int32_t j0 = 0; j0 < cnt; j0 += kT) {
+        if (j0 >= sa && j0 + kT <= sb) continue;  // kT skipped points
         const int32_t jj = j0 + sub;
         const bool in = jj < cnt && !(jj >= sa && jj < sb);
         const Cand q = stage[in ? jj : 0];
@@ -1042,7 +1068,7 @@ constexpr size_t wave_lds_bytes() {
 // (21.7 against 17.6 ms).
 template <int K>
 constexpr bool all_team() {
-  return K >= 20;
+  return team_size<K>() > 0;
 }
 template <int K>
 constexpr size_t all_lds_bytes() {
@@ -1079,18 +1105,18 @@ __device__ __forceinline__ void bind_lds(WaveSearch<D, K, E, P, TM> &s, char *sm
 // capped at 96 gives 5 and measured 7% faster.  The lane-team buckets
 // (k >= 17) trade a few spilled dwords for occupancy, 10M uniform points:
 // k = 20 at 80 VGPRs (6 per SIMD) 24.3 -> 23.4 ms, k = 24, 32 and 40 at 96
-// (5) 29.8 -> 27.3, 36.0 -> 33.9 and 53.1 -> 45.2 ms, k = 50 and 64 at 128
-// (4) 67.3 -> 60.2 and 111.9 -> 83.4 ms, k = 100 at 256 (2) 336 -> 194 ms
-// (at 168, 173 spilled dwords: 209 ms).  Other buckets keep the compiler's
+// (5) 29.8 -> 27.3, 36.0 -> 33.9 and 53.1 -> 45.2 ms, k = 50 at 128 (4)
+// 67.3 -> 60.2 ms; in teams of 8, k = 64 at 96 (5) 81.3 -> 75.7 ms and
+// k = 100 at 128 (4) 157.0 -> 138.6 ms.  Other buckets keep the compiler's
 // choice (caps that spill inside the insertion, k = 12 at 80 or k = 16 at
 // 96, run up to twice as long).
 template <int K>
 constexpr int knn_all_min_waves() {
   return K == 10 || K == 20 ? 6
          : K == 12 || K == 24 || K == 32 || K == 40 ? 5
-         : K == 50 || K == 64 ? 4
-         : K == 100 ? 2
-                    : 1;
+         : K == 64 ? 5
+         : K == 50 || K == 100 ? 4
+                               : 1;
 }
 
 // The all-points rows of sorted positions [g0, last] (at most 64), which
@@ -1146,21 +1172,22 @@ __device__ __forceinline__ void all_points_lanes(const TreeView &t, int k,
 }
 
 // The same rows in lane teams (TeamSet): sorted positions [g0, last], at
-// most 16, one query per four lanes.
+// most 64 / T, one query per T lanes.
 template <int D, int K, bool kPool>
 __device__ __forceinline__ void all_points_team(const TreeView &t, int k,
                                                 int32_t *__restrict__ out_ids,
                                                 double *__restrict__ out_d2, int64_t g0,
                                                 int64_t last, int64_t c_lo, int64_t c_hi,
                                                 char *smem, int w) {
+  constexpr int T = team_size<K>();
   const int lane = threadIdx.x & 63;
-  const int64_t i = min(g0 + (lane >> 2), last);
+  const int64_t i = min(g0 + lane / T, last);
   WaveSearch<D, K, false, kPool, true> s(t, nullptr);
   bind_lds(s, smem, w);
   s.px = t.X[i];
   s.py = t.Y[i];
   s.pz = D == 3 ? t.Z[i] : 0.0;
-  s.valid = g0 + (lane >> 2) <= last && !isnan(s.px);
+  s.valid = g0 + lane / T <= last && !isnan(s.px);
   s.self = t.id[i];
   const int mid = (int)((last - g0) / 2);
   s.budget = t.walk_limit > 0 ? t.walk_limit : 4 * t.n + 256;
@@ -1186,8 +1213,7 @@ __device__ __forceinline__ void all_points_team(const TreeView &t, int k,
 
 // One wavefront answers the all-points rows of sorted positions [g0, last]
 // (at most 64) of the cloud [c_lo, c_hi]: in one group of 64 lanes, or,
-// for the team buckets, in up to four groups of 16 queries one after the
-// other.
+// for the team buckets, in groups of 64 / T queries one after the other.
 template <int D, int K, bool kPool>
 __device__ __forceinline__ void all_points_group(const TreeView &t, int k,
                                                  int32_t *__restrict__ out_ids,
@@ -1195,8 +1221,9 @@ __device__ __forceinline__ void all_points_group(const TreeView &t, int k,
                                                  int64_t last, int64_t c_lo, int64_t c_hi,
                                                  char *smem, int w) {
   if constexpr (all_team<K>()) {
-    for (int64_t sg = g0; sg <= last; sg += 16)
-      all_points_team<D, K, kPool>(t, k, out_ids, out_d2, sg, min(sg + 15, last), c_lo, c_hi,
+    constexpr int Q = 64 / team_size<K>();  // queries per team group
+    for (int64_t sg = g0; sg <= last; sg += Q)
+      all_points_team<D, K, kPool>(t, k, out_ids, out_d2, sg, min(sg + Q - 1, last), c_lo, c_hi,
                                    smem, w);
   } else {
     all_points_lanes<D, K, kPool>(t, k, out_ids, out_d2, g0, last, c_lo, c_hi, smem, w);
