@@ -594,6 +594,14 @@ template <int K>
 constexpr int team_size() {
   return K > 50 ? 8 : (K > 16 ? 4 : 0);
 }
+// The same for external queries, which gain from teams from k = 8 on (1M
+// queries into 10M uniform points, rows identical: k = 8 / 10 / 12 / 16 in
+// 4.30 / 4.65 / 5.00 / 6.55 ms against 4.46 / 5.19 / 5.99 / 8.53 ms with
+// one lane per query; k = 4: 3.58 against 3.12 ms).
+template <int K>
+constexpr int ext_team_size() {
+  return K > 16 ? team_size<K>() : (K >= 8 ? 4 : 0);
+}
 
 // Per k bucket: the candidate set, its per-lane LDS slots, whether the
 // prescore runs in the shared order over a 64-entry stage (the LDS heap)
@@ -676,7 +684,6 @@ struct Cand {
 // The per-lane state of one wavefront's shared search.
 template <int D, int K, bool kExt = false, bool kPool = false, bool kTeam = false>
 struct WaveSearch {
-  static_assert(!(kTeam && kExt), "lane teams serve the all-points rows only");
   const TreeView &t;
   Cand *stage;                   // this wavefront's 64-entry LDS slice (candidates)
   double px, py, pz;             // this lane's query
@@ -688,7 +695,9 @@ struct WaveSearch {
   int64_t budget;                // walk bound (never reached on a valid tree)
   bool gave_up = false;          // the walk stopped before it finished
   uint64_t key_ref;              // Morton key of the group's middle query (child order)
-  static constexpr int kT = team_size<K>() > 0 ? team_size<K>() : 4;  // lanes per query in teams
+  // lanes per query in teams
+  static constexpr int kTS = kExt ? ext_team_size<K>() : team_size<K>();
+  static constexpr int kT = kTS > 0 ? kTS : 4;
   std::conditional_t<kTeam, TeamSet<K, kT>, typename HeapFor<K>::type> h;
   __device__ __forceinline__ WaveSearch(const TreeView &t_, Cand *stage_) : t(t_), stage(stage_) {}
 
@@ -871,7 +880,15 @@ struct WaveSearch {
       for (int32_t j0 = 0; j0 < cnt; j0 += kT) {
         if (j0 >= sa && j0 + kT <= sb) continue;  // kT skipped points
         const int32_t jj = j0 + sub;
-        const bool in = jj < cnt && !(jj >= sa && jj < sb);
+        bool in = jj < cnt && !(jj >= sa && jj < sb);
+        if constexpr (kExt) {
+          // a point of the query's own leaf was scored before the walk; a
+          // pool query never scores its own entry
+          const int32_t pos = c + jj;
+          const bool seen = !kPool || pos < e ? (uint32_t)(pos - own_lo) < (uint32_t)own_n
+                                              : pb + (pos - e) == own_pool;
+          in = in && !seen;
+        }
         const Cand q = stage[in ? jj : 0];
         const double dd = dist2<D>(px, py, pz, q.x, q.y, q.z);
         h.offer_team(in ? dd : INFINITY, in ? q.id : INT_MAX);
@@ -1257,37 +1274,47 @@ k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
 
 // External rows: wavefront w answers the Morton-sorted queries
 // order[64w .. 64w + 64); row r of the output belongs to query r.
-// Register budget of the external-query kernel: k = 16 capped at 128 VGPRs
-// (4 wavefronts per SIMD instead of 3) and k = 24 and 32 at 168 (3 instead
-// of 2) measured 9-12% faster; k = 40 capped at 168 ran 8% slower and keeps
-// the compiler's choice, like the other buckets.
+// Register budget of the external-query kernel: in lane teams (k >= 8) the
+// all-points kernel's caps; the root-based kernel, one lane per query,
+// keeps its own: k = 16 capped at 128 VGPRs (4 wavefronts per SIMD instead
+// of 3) and k = 24 and 32 at 168 (3 instead of 2) measured 9-12% faster
+// with one lane per query; k = 40 capped at 168 ran 8% slower and keeps the
+// compiler's choice, like the other buckets.
 template <int K>
-constexpr int knn_ext_min_waves() {
+constexpr bool ext_team() {
+  return ext_team_size<K>() > 0;
+}
+template <int K>
+constexpr int knn_root_min_waves() {
   return K == 16 ? 4 : (K == 24 || K == 32 ? 3 : 1);
 }
+template <int K>
+constexpr int knn_ext_min_waves() {
+  return ext_team<K>() ? knn_all_min_waves<K>() : knn_root_min_waves<K>();
+}
 
-template <int D, int K, bool kPool>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(knn_ext_min_waves<K>())))
-k_knn_ext(TreeView t, const double *__restrict__ q, int64_t qs,
-                                                 const uint64_t *__restrict__ qkey,
-                                                 const int32_t *__restrict__ order, int64_t m,
-                                                 int k, int32_t *__restrict__ out_ids,
-                                                 double *__restrict__ out_d2,
-                                                 const int32_t *__restrict__ row_ids) {
-  extern __shared__ __align__(16) char smem[];
+// One wavefront's external rows for the Morton-sorted queries
+// order[g0 .. last]: up to 64 with one lane per query, or up to 64 / T in
+// lane teams (kTeam).
+template <int D, int K, bool kPool, bool kTeam>
+__device__ __forceinline__ void ext_group(const TreeView &t, const double *__restrict__ q,
+                                          int64_t qs, const uint64_t *__restrict__ qkey,
+                                          const int32_t *__restrict__ order, int64_t g0,
+                                          int64_t last, int k, int32_t *__restrict__ out_ids,
+                                          double *__restrict__ out_d2,
+                                          const int32_t *__restrict__ row_ids, char *smem, int w) {
+  using Search = WaveSearch<D, K, true, kPool, kTeam>;
+  constexpr int T = kTeam ? Search::kT : 1;
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int64_t g0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + w) * 64;
-  if (g0 >= m) return;
-  const int64_t last = min(g0 + 63, m - 1);
-  const int64_t i = min(g0 + lane, last);
+  const int sub = lane % T;
+  const int64_t i = min(g0 + lane / T, last);
   const int32_t r = order[i];
-  WaveSearch<D, K, true, kPool> s(t, nullptr);
+  Search s(t, nullptr);
   bind_lds(s, smem, w);
   s.px = q[r];
   s.py = q[qs + r];
   s.pz = D == 3 ? q[2 * qs + r] : 0.0;
-  s.valid = g0 + lane <= last;
+  s.valid = g0 + lane / T <= last;
   // row_ids: the queries are the tree's own pool entries (points of small
   // inserts): row = the point's id, the entry itself excluded, a deleted
   // entry (NaN) answers nothing
@@ -1318,10 +1345,10 @@ k_knn_ext(TreeView t, const double *__restrict__ q, int64_t qs,
       if (b0 != b1) break;
       node = uni(N->child[b0]);
     }
-    // every lane first scores the leaf its own key leads to (the bit-based
-    // descent of Section 2, per lane), which gives each lane a k-th
-    // distance from its own neighbourhood before the shared walk; the walk
-    // skips those points for that lane
+    // every query first scores the leaf its own key leads to (the bit-based
+    // descent of Section 2, per query), which gives it a k-th distance from
+    // its own neighbourhood before the shared walk; the walk skips those
+    // points for that query (a team's lanes take every T-th of them)
     {
       const uint64_t myk = qkey[i];
       int32_t x = node;
@@ -1336,19 +1363,47 @@ k_knn_ext(TreeView t, const double *__restrict__ q, int64_t qs,
       const int32_t lb = x < 0 ? t.leaf_begin[~x] : 0, le = x < 0 ? t.leaf_begin[~x + 1] : 0;
       s.own_lo = lb;
       s.own_n = s.valid ? le - lb : 0;
-      const int rounds = wave_max(s.own_n);
-      for (int jj = 0; jj < rounds; ++jj) {
+      const int rounds = wave_max((s.own_n + T - 1) / T);
+      for (int rr = 0; rr < rounds; ++rr) {
+        const int jj = rr * T + sub;
         const bool in = jj < s.own_n;
         const int64_t j = lb + (in ? jj : 0);
         const double dd = dist2<D>(s.px, s.py, s.pz, t.X[j], t.Y[j], D == 3 ? t.Z[j] : 0.0);
         const int32_t q = t.id[j];
-        s.h.template offer<true>(in ? dd : INFINITY, in ? q : INT_MAX);
+        if constexpr (kTeam)
+          s.h.offer_team(in ? dd : INFINITY, in ? q : INT_MAX);
+        else
+          s.h.template offer<true>(in ? dd : INFINITY, in ? q : INT_MAX);
       }
     }
     s.run_from(node);
     s.report();
   }
   if (s.valid) s.h.write(k, out_ids + row * k, out_d2 + row * k);
+}
+
+template <int D, int K, bool kPool>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(knn_ext_min_waves<K>())))
+k_knn_ext(TreeView t, const double *__restrict__ q, int64_t qs,
+                                                 const uint64_t *__restrict__ qkey,
+                                                 const int32_t *__restrict__ order, int64_t m,
+                                                 int k, int32_t *__restrict__ out_ids,
+                                                 double *__restrict__ out_d2,
+                                                 const int32_t *__restrict__ row_ids) {
+  extern __shared__ __align__(16) char smem[];
+  const int w = threadIdx.x >> 6;
+  const int64_t g0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + w) * 64;
+  if (g0 >= m) return;
+  const int64_t last = min(g0 + 63, m - 1);
+  if constexpr (ext_team<K>()) {
+    constexpr int Q = 64 / WaveSearch<D, K, true, kPool, true>::kT;  // queries per team group
+    for (int64_t sg = g0; sg <= last; sg += Q)
+      ext_group<D, K, kPool, true>(t, q, qs, qkey, order, sg, min(sg + Q - 1, last), k, out_ids,
+                                   out_d2, row_ids, smem, w);
+  } else {
+    ext_group<D, K, kPool, false>(t, q, qs, qkey, order, g0, last, k, out_ids, out_d2, row_ids,
+                                  smem, w);
+  }
 }
 
 // Root-based rows (Section 2): Algorithm 2 from the root with an empty
@@ -1359,7 +1414,7 @@ k_knn_ext(TreeView t, const double *__restrict__ q, int64_t qs,
 // Morton-presorted external queries as in k_knn_ext.  The shared walk is the
 // same as everywhere else; only its start differs.
 template <int D, int K, bool kPool>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(knn_ext_min_waves<K>())))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(knn_root_min_waves<K>())))
 k_knn_root(TreeView t, const double *__restrict__ q, int64_t qs, const uint64_t *__restrict__ qkey,
            const int32_t *__restrict__ order, int64_t m, int k, int32_t *__restrict__ out_ids,
            double *__restrict__ out_d2, const int32_t *__restrict__ row_ids) {
@@ -1455,14 +1510,13 @@ hipError_t launch_knn_ext(const TreeView &t, const double *q, int64_t qs, const 
                           const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
                           const int32_t *row_ids, hipStream_t s, int query_waves) {
   const int64_t waves = (m + 63) / 64;
-  const int wpb = fit_waves<K>(query_waves);
+  const int wpb = fit_waves<K, ext_team<K>()>(query_waves);
+  const size_t lds = wpb * (ext_team<K>() ? all_lds_bytes<K>() : wave_lds_bytes<K>());
   const dim3 grid((unsigned)((waves + wpb - 1) / wpb)), block(64 * wpb);
   if (t.ovf_cnt)
-    k_knn_ext<D, K, true><<<grid, block, wpb * wave_lds_bytes<K>(), s>>>(t, q, qs, qkey, order, m,
-                                                                         k, ids, d2, row_ids);
+    k_knn_ext<D, K, true><<<grid, block, lds, s>>>(t, q, qs, qkey, order, m, k, ids, d2, row_ids);
   else
-    k_knn_ext<D, K, false><<<grid, block, wpb * wave_lds_bytes<K>(), s>>>(t, q, qs, qkey, order, m,
-                                                                          k, ids, d2, row_ids);
+    k_knn_ext<D, K, false><<<grid, block, lds, s>>>(t, q, qs, qkey, order, m, k, ids, d2, row_ids);
   return hipGetLastError();
 }
 
