@@ -594,10 +594,11 @@ template <int K>
 constexpr int team_size() {
   return K > 50 ? 8 : (K > 16 ? 4 : 0);
 }
-// The same for external queries, which gain from teams from k = 8 on (1M
-// queries into 10M uniform points, rows identical: k = 8 / 10 / 12 / 16 in
-// 4.30 / 4.65 / 5.00 / 6.55 ms against 4.46 / 5.19 / 5.99 / 8.53 ms with
-// one lane per query; k = 4: 3.58 against 3.12 ms).
+// The same for external queries, whose sparse sets gain from teams from
+// k = 8 on (1M queries into 10M uniform points, rows identical: k = 8 / 10
+// / 12 / 16 in 4.30 / 4.65 / 5.00 / 6.55 ms against 4.46 / 5.19 / 5.99 /
+// 8.53 ms with one lane per query; k = 4: 3.58 against 3.12 ms); see
+// launch_knn_ext for the choice at k = 8-16.
 template <int K>
 constexpr int ext_team_size() {
   return K > 16 ? team_size<K>() : (K >= 8 ? 4 : 0);
@@ -1281,16 +1282,12 @@ k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
 // with one lane per query; k = 40 capped at 168 ran 8% slower and keeps the
 // compiler's choice, like the other buckets.
 template <int K>
-constexpr bool ext_team() {
-  return ext_team_size<K>() > 0;
-}
-template <int K>
 constexpr int knn_root_min_waves() {
   return K == 16 ? 4 : (K == 24 || K == 32 ? 3 : 1);
 }
-template <int K>
+template <int K, bool kTeam>
 constexpr int knn_ext_min_waves() {
-  return ext_team<K>() ? knn_all_min_waves<K>() : knn_root_min_waves<K>();
+  return kTeam ? knn_all_min_waves<K>() : knn_root_min_waves<K>();
 }
 
 // One wavefront's external rows for the Morton-sorted queries
@@ -1382,8 +1379,8 @@ __device__ __forceinline__ void ext_group(const TreeView &t, const double *__res
   if (s.valid) s.h.write(k, out_ids + row * k, out_d2 + row * k);
 }
 
-template <int D, int K, bool kPool>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(knn_ext_min_waves<K>())))
+template <int D, int K, bool kPool, bool kTeam>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(knn_ext_min_waves<K, kTeam>())))
 k_knn_ext(TreeView t, const double *__restrict__ q, int64_t qs,
                                                  const uint64_t *__restrict__ qkey,
                                                  const int32_t *__restrict__ order, int64_t m,
@@ -1395,7 +1392,7 @@ k_knn_ext(TreeView t, const double *__restrict__ q, int64_t qs,
   const int64_t g0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + w) * 64;
   if (g0 >= m) return;
   const int64_t last = min(g0 + 63, m - 1);
-  if constexpr (ext_team<K>()) {
+  if constexpr (kTeam) {
     constexpr int Q = 64 / WaveSearch<D, K, true, kPool, true>::kT;  // queries per team group
     for (int64_t sg = g0; sg <= last; sg += Q)
       ext_group<D, K, kPool, true>(t, q, qs, qkey, order, sg, min(sg + Q - 1, last), k, out_ids,
@@ -1505,19 +1502,46 @@ hipError_t launch_knn_all(const TreeView &t, int k, int32_t *ids, double *d2, hi
   return hipGetLastError();
 }
 
+template <int D, int K, bool kTeam>
+hipError_t launch_knn_ext_as(const TreeView &t, const double *q, int64_t qs, const uint64_t *qkey,
+                             const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
+                             const int32_t *row_ids, hipStream_t s, int query_waves) {
+  const int64_t waves = (m + 63) / 64;
+  const int wpb = fit_waves<K, kTeam>(query_waves);
+  const size_t lds = wpb * (kTeam ? all_lds_bytes<K>() : wave_lds_bytes<K>());
+  const dim3 grid((unsigned)((waves + wpb - 1) / wpb)), block(64 * wpb);
+  if (t.ovf_cnt)
+    k_knn_ext<D, K, true, kTeam>
+        <<<grid, block, lds, s>>>(t, q, qs, qkey, order, m, k, ids, d2, row_ids);
+  else
+    k_knn_ext<D, K, false, kTeam>
+        <<<grid, block, lds, s>>>(t, q, qs, qkey, order, m, k, ids, d2, row_ids);
+  return hipGetLastError();
+}
+
+// External queries run in lane teams from k = 17 on, and at k = 8-16 when
+// they are sparse next to the tree (at most a quarter as many queries as
+// points): a 64-query group of sparse queries spans many leaves, which the
+// teams' 16-query groups cut, while dense queries (the tree's own points as
+// queries, 10M into 10M) ran slower in teams at k <= 16 (uniform k = 10:
+// 22.6 against 18.4 ms; Plummer 24.0 against 17.3; at k = 20: 29.2
+// against 36.1 and 30.5 against 34.2 ms).
 template <int D, int K>
 hipError_t launch_knn_ext(const TreeView &t, const double *q, int64_t qs, const uint64_t *qkey,
                           const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
                           const int32_t *row_ids, hipStream_t s, int query_waves) {
-  const int64_t waves = (m + 63) / 64;
-  const int wpb = fit_waves<K, ext_team<K>()>(query_waves);
-  const size_t lds = wpb * (ext_team<K>() ? all_lds_bytes<K>() : wave_lds_bytes<K>());
-  const dim3 grid((unsigned)((waves + wpb - 1) / wpb)), block(64 * wpb);
-  if (t.ovf_cnt)
-    k_knn_ext<D, K, true><<<grid, block, lds, s>>>(t, q, qs, qkey, order, m, k, ids, d2, row_ids);
+  if constexpr (ext_team_size<K>() == 0)
+    return launch_knn_ext_as<D, K, false>(t, q, qs, qkey, order, m, k, ids, d2, row_ids, s,
+                                          query_waves);
+  else if constexpr (K > 16)
+    return launch_knn_ext_as<D, K, true>(t, q, qs, qkey, order, m, k, ids, d2, row_ids, s,
+                                         query_waves);
+  else if (4 * m <= t.n)
+    return launch_knn_ext_as<D, K, true>(t, q, qs, qkey, order, m, k, ids, d2, row_ids, s,
+                                         query_waves);
   else
-    k_knn_ext<D, K, false><<<grid, block, lds, s>>>(t, q, qs, qkey, order, m, k, ids, d2, row_ids);
-  return hipGetLastError();
+    return launch_knn_ext_as<D, K, false>(t, q, qs, qkey, order, m, k, ids, d2, row_ids, s,
+                                          query_waves);
 }
 
 // K buckets: a k between two buckets runs in the larger one (the padding

@@ -73,3 +73,22 @@ def test_every_bucket_matches_brute_force(k, bucket, data, dim, mode):
                     f"{data}{dim} {mode} k={k}")
     t.check()
     t.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("data", ["grid", "clustered"])
+@pytest.mark.parametrize("k,bucket", [(k, b) for k, b in bucket_cases() if 8 <= b <= 16],
+                         ids=[f"k{k}-b{b}" for k, b in bucket_cases() if 8 <= b <= 16])
+def test_sparse_external_queries(k, bucket, data, dim):
+    """External queries at most a quarter as many as the tree's points run
+    in lane teams at k = 8-16 (denser ones, as in the test above, one lane
+    per query): the same rows as brute force."""
+    P, Q = case(data, dim)
+    Qs = Q[: len(P) // 5]
+    assert 4 * len(Qs) <= len(P)
+    print(f"bucket {bucket} k={k} {data} {dim}D sparse ext m={len(Qs)} n={len(P)}", flush=True)
+    t = zd.ZdTree(dev(P), leaf_size=8, shift_seed=bucket)
+    assert_rows(t.knn(k, dev(Qs)), oracle.brute_knn(P, k, queries=Qs),
+                f"{data}{dim} sparse ext k={k}")
+    t.check()
+    t.close()
