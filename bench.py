@@ -100,8 +100,8 @@ PAPER_BUILD_QUERY_K10_QPS = 10_000_000 / 0.453  # CPU context only (144 threads)
 # They describe the kernel sources whose code (comments stripped) has this
 # sha1 only; after any change to that code the figure is reported as null
 # until the counters are taken again.
-KNN_TRAFFIC = {"sources_sha1": "7fbf09d6fca6c6e6791944443f6cc0150dc7850a",
-               "fetch_bytes": 2.017e+09, "write_bytes": 2.291e+09}
+KNN_TRAFFIC = {"sources_sha1": "dd49fbf02bf8ef8454eaf5eb6515de400d4f6ef8",
+               "fetch_bytes": 2.016e+09, "write_bytes": 2.292e+09}
 TRAFFIC_LEAF = 24  # leaf size of the profiled run
 KNN_SOURCES = ("paper_2111_04182_amd/csrc/zd_knn_impl.h", "paper_2111_04182_amd/csrc/zd_internal.h",
                "paper_2111_04182_amd/csrc/zd_sortnet.h", "paper_2111_04182_amd/csrc/zd_knn_all_d3.hip")
@@ -670,12 +670,15 @@ def leg_grad(fd_coords=1000):
         # the same in the tree's Morton order (while no in-place batch is
         # pending, as after the build and after a fold)
         if tree.pending() == (0, 0):
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-            e[0].record()
-            gt = tree.knn_backward(ids, g)
-            e[1].record()
-            torch.cuda.synchronize()
-            times["backward_tree_order"].append(e[0].elapsed_time(e[1]))
+            # five calls: the first one also takes its scratch buffer from
+            # the library's caching allocator
+            for _ in range(5):
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                e[0].record()
+                gt = tree.knn_backward(ids, g)
+                e[1].record()
+                torch.cuda.synchronize()
+                times["backward_tree_order"].append(e[0].elapsed_time(e[1]))
             tree_vs_id_order = max(tree_vs_id_order, float((gt - gx).abs().max() /
                                                            gx.abs().max().clamp(min=1.0)))
         # the autograd function end to end (torch's masking and sum included)
@@ -732,7 +735,7 @@ def leg_grad(fd_coords=1000):
     med = {kk: float(np.median(v)) if v else None for kk, v in times.items()}
     return {"n": n0, "k": k, "median_ms": med, "fwd_bwd_points_per_s":
             n0 / (med["forward"] + med["backward"]) * 1e3, "fd_checked": checked,
-            "fd_max_rel_err": worst, "backward_tree_order_rounds": len(times["backward_tree_order"]),
+            "fd_max_rel_err": worst, "backward_tree_order_calls": len(times["backward_tree_order"]),
             "backward_tree_vs_id_order_max_rel_diff": tree_vs_id_order}
 
 
