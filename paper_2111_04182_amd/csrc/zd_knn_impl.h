@@ -1275,12 +1275,11 @@ k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
 
 // External rows: wavefront w answers the Morton-sorted queries
 // order[64w .. 64w + 64); row r of the output belongs to query r.
-// Register budget of the external-query kernel: in lane teams (k >= 8) the
-// all-points kernel's caps; the root-based kernel, one lane per query,
-// keeps its own: k = 16 capped at 128 VGPRs (4 wavefronts per SIMD instead
-// of 3) and k = 24 and 32 at 168 (3 instead of 2) measured 9-12% faster
-// with one lane per query; k = 40 capped at 168 ran 8% slower and keeps the
-// compiler's choice, like the other buckets.
+// Register budget of the external-query and root-based kernels: in lane
+// teams the all-points kernel's caps; with one lane per query: k = 16
+// capped at 128 VGPRs (4 wavefronts per SIMD instead of 3) and k = 24 and
+// 32 at 168 (3 instead of 2) measured 9-12% faster; k = 40 capped at 168 ran
+// 8% slower and keeps the compiler's choice, like the other buckets.
 template <int K>
 constexpr int knn_root_min_waves() {
   return K == 16 ? 4 : (K == 24 || K == 32 ? 3 : 1);
@@ -1410,22 +1409,25 @@ k_knn_ext(TreeView t, const double *__restrict__ q, int64_t qs,
 // excluded (a one-point "own" range of the external-query scan); otherwise
 // Morton-presorted external queries as in k_knn_ext.  The shared walk is the
 // same as everywhere else; only its start differs.
-template <int D, int K, bool kPool>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(knn_root_min_waves<K>())))
-k_knn_root(TreeView t, const double *__restrict__ q, int64_t qs, const uint64_t *__restrict__ qkey,
-           const int32_t *__restrict__ order, int64_t m, int k, int32_t *__restrict__ out_ids,
-           double *__restrict__ out_d2, const int32_t *__restrict__ row_ids) {
-  extern __shared__ __align__(16) char smem[];
+
+// One wavefront's root-based rows for positions [g0, last] (sorted tree
+// positions, or Morton-sorted external queries): up to 64 with one lane per
+// query, or up to 64 / T in lane teams (kTeam).
+template <int D, int K, bool kPool, bool kTeam>
+__device__ __forceinline__ void root_group(const TreeView &t, const double *__restrict__ q,
+                                           int64_t qs, const uint64_t *__restrict__ qkey,
+                                           const int32_t *__restrict__ order, int64_t g0,
+                                           int64_t last, int k, int32_t *__restrict__ out_ids,
+                                           double *__restrict__ out_d2,
+                                           const int32_t *__restrict__ row_ids, char *smem, int w) {
+  using Search = WaveSearch<D, K, true, kPool, kTeam>;
+  constexpr int T = kTeam ? Search::kT : 1;
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int64_t g0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + w) * 64;
-  if (g0 >= m) return;
-  const int64_t last = min(g0 + 63, m - 1);
-  const int64_t i = min(g0 + lane, last);
+  const int64_t i = min(g0 + lane / T, last);
   const int mid = (int)((last - g0) / 2);
-  WaveSearch<D, K, true, kPool> s(t, nullptr);
+  Search s(t, nullptr);
   bind_lds(s, smem, w);
-  s.valid = g0 + lane <= last;
+  s.valid = g0 + lane / T <= last;
   int64_t row;
   uint64_t kref;
   if (q) {
@@ -1470,20 +1472,43 @@ k_knn_root(TreeView t, const double *__restrict__ q, int64_t qs, const uint64_t 
   if (s.valid) s.h.write(k, out_ids + row * k, out_d2 + row * k);
 }
 
+// Root-based rows in lane teams at k > 16, as the leaf-based all-points rows.
+template <int D, int K, bool kPool>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    team_size<K>() > 0 ? knn_all_min_waves<K>() : knn_root_min_waves<K>())))
+k_knn_root(TreeView t, const double *__restrict__ q, int64_t qs, const uint64_t *__restrict__ qkey,
+           const int32_t *__restrict__ order, int64_t m, int k, int32_t *__restrict__ out_ids,
+           double *__restrict__ out_d2, const int32_t *__restrict__ row_ids) {
+  extern __shared__ __align__(16) char smem[];
+  const int w = threadIdx.x >> 6;
+  const int64_t g0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + w) * 64;
+  if (g0 >= m) return;
+  const int64_t last = min(g0 + 63, m - 1);
+  if constexpr (team_size<K>() > 0) {
+    constexpr int Q = 64 / WaveSearch<D, K, true, kPool, true>::kT;  // queries per team group
+    for (int64_t sg = g0; sg <= last; sg += Q)
+      root_group<D, K, kPool, true>(t, q, qs, qkey, order, sg, min(sg + Q - 1, last), k, out_ids,
+                                    out_d2, row_ids, smem, w);
+  } else {
+    root_group<D, K, kPool, false>(t, q, qs, qkey, order, g0, last, k, out_ids, out_d2, row_ids,
+                                   smem, w);
+  }
+}
+
 template <int D, int K>
 hipError_t launch_knn_root(const TreeView &t, const double *q, int64_t qs, const uint64_t *qkey,
                            const int32_t *order, int64_t m, int k, int32_t *ids, double *d2,
                            const int32_t *row_ids, hipStream_t s, int query_waves) {
+  constexpr bool kTeam = team_size<K>() > 0;
   const int64_t waves = (m + 63) / 64;
-  const int wpb = fit_waves<K>(query_waves);
+  const int wpb = fit_waves<K, kTeam>(query_waves);
+  const size_t lds = wpb * (kTeam ? all_lds_bytes<K>() : wave_lds_bytes<K>());
   // (the variant that scans leaves' side blocks only while small inserts are pending)
   const dim3 grid((unsigned)((waves + wpb - 1) / wpb)), block(64 * wpb);
   if (t.ovf_cnt)
-    k_knn_root<D, K, true><<<grid, block, wpb * wave_lds_bytes<K>(), s>>>(t, q, qs, qkey, order, m,
-                                                                          k, ids, d2, row_ids);
+    k_knn_root<D, K, true><<<grid, block, lds, s>>>(t, q, qs, qkey, order, m, k, ids, d2, row_ids);
   else
-    k_knn_root<D, K, false><<<grid, block, wpb * wave_lds_bytes<K>(), s>>>(t, q, qs, qkey, order, m,
-                                                                           k, ids, d2, row_ids);
+    k_knn_root<D, K, false><<<grid, block, lds, s>>>(t, q, qs, qkey, order, m, k, ids, d2, row_ids);
   return hipGetLastError();
 }
 
