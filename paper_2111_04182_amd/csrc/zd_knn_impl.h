@@ -50,6 +50,7 @@ namespace zd {
 // no box is ever within its k-th distance, so it needs no test of its own.
 template <int K>
 struct Heap {
+  static_assert(K <= 16, "one lane per query serves k <= 16; larger k run in lane teams");
   double d[K];
   int32_t id[K];
 
@@ -64,25 +65,6 @@ struct Heap {
 
   __device__ __forceinline__ double kth() const { return d[K - 1]; }
 
-  // lt[j - A] = (dd, q) precedes slot j, for j in [A, B).  The distance
-  // compare decides unless the distances are equal; the id compares run
-  // only when some lane meets an equal distance in the range.  (Used by the
-  // segmented shift; for k <= 16 the three compares per slot measured
-  // faster than the extra branch.)
-  template <int A, int B>
-  __device__ __forceinline__ void precedes(double dd, int32_t q, bool *lt) const {
-    bool tie = false;
-#pragma unroll
-    for (int j = A; j < B; ++j) {
-      lt[j - A] = dd < d[j];
-      tie = tie | (dd == d[j]);
-    }
-    if (__ballot(tie) != 0) {
-#pragma unroll
-      for (int j = A; j < B; ++j) lt[j - A] = lt[j - A] | ((dd == d[j]) & (q < id[j]));
-    }
-  }
-
   // insert(N, q, k) of Algorithms 2-3: enters iff it precedes the k-th entry.
   // The first test is one compare; a tie with the k-th distance falls through
   // to the exact (d2, id) comparisons, which then change nothing if the
@@ -90,9 +72,7 @@ struct Heap {
   template <bool kSplit = false>
   __device__ __forceinline__ void offer(double dd, int32_t q) {
     if (!(dd <= d[K - 1])) return;
-    if constexpr (K >= kSegFrom) {
-      this->template shift_seg<K>(dd, q);
-    } else if constexpr (kSplit && K >= 8) {
+    if constexpr (kSplit && K >= 8) {
       offer_split(dd, q);
     } else {
       bool lt[K];
@@ -102,49 +82,6 @@ struct Heap {
       for (int j = K - 1; j > 0; --j) {
         // slot j takes its left neighbour if the candidate precedes that
         // neighbour, else the candidate if it precedes slot j, else stays
-        const double nd = lt[j - 1] ? d[j - 1] : (lt[j] ? dd : d[j]);
-        const int32_t ni = lt[j - 1] ? id[j - 1] : (lt[j] ? q : id[j]);
-        d[j] = nd;
-        id[j] = ni;
-      }
-      if (lt[0]) {
-        d[0] = dd;
-        id[0] = q;
-      }
-    }
-  }
-
-  // For k in (16, 24]: the shift in segments of kSeg slots, top segment
-  // first.  Segment [A, B) always shifts (its lowest slot takes slot A-1's
-  // old entry if the candidate precedes that entry), and the segment below
-  // runs only when some lane's candidate does.  Most entries land near the
-  // k-th slot, so most insertions touch one segment.
-  static constexpr int kSegFrom = 20;
-  static constexpr int kSeg = 8;
-  template <int B>
-  __device__ __forceinline__ void shift_seg(double dd, int32_t q) {
-    constexpr int A = B > kSeg ? B - kSeg : 0;
-    bool lt[B - A];
-    precedes<A, B>(dd, q, lt);
-    if constexpr (A > 0) {
-      const bool low = cand_lt(dd, q, d[A - 1], id[A - 1]);
-      const double cd = d[A - 1];
-      const int32_t ci = id[A - 1];
-#pragma unroll
-      for (int j = B - 1; j > A; --j) {
-        const double nd = lt[j - 1 - A] ? d[j - 1] : (lt[j - A] ? dd : d[j]);
-        const int32_t ni = lt[j - 1 - A] ? id[j - 1] : (lt[j - A] ? q : id[j]);
-        d[j] = nd;
-        id[j] = ni;
-      }
-      const double nd = low ? cd : (lt[0] ? dd : d[A]);
-      const int32_t ni = low ? ci : (lt[0] ? q : id[A]);
-      d[A] = nd;
-      id[A] = ni;
-      if (__ballot(low) != 0) this->template shift_seg<A>(dd, q);
-    } else {
-#pragma unroll
-      for (int j = B - 1; j > 0; --j) {
         const double nd = lt[j - 1] ? d[j - 1] : (lt[j] ? dd : d[j]);
         const int32_t ni = lt[j - 1] ? id[j - 1] : (lt[j] ? q : id[j]);
         d[j] = nd;
@@ -230,224 +167,6 @@ struct Heap {
         out_ids[o] = id[j] == INT_MAX ? -1 : id[j];
         out_d2[o] = d[j];
       }
-  }
-};
-
-// For external and root-based queries with k > 50 (up to 100, the largest
-// k of the paper's sweep; the all-points rows use TeamSet) the candidate
-// set is a binary max-heap of the k best (d2, id) per lane, kept in LDS
-// (slot-major: slot s of lane l at [s * 64 + l], so a lane's bank never
-// depends on the slot it touches): the heap the paper switches to for large
-// k (Section 3.1).  Replacing the root and sifting down costs O(log k)
-// instead of the O(k) register shift, and the register file stays small.
-// The root (the k-th entry) is mirrored in registers for the entry test;
-// the rows are produced by one heap sort.  At k = 100 a wavefront's heaps
-// take 77 KB of LDS, so two wavefronts share a CU.
-template <int K>
-struct LdsHeap {
-  double *hd;     // [K][64] this wavefront's distances
-  int32_t *hi;    // [K][64] this wavefront's ids
-  int k;
-  double root_d;
-  int32_t root_i;
-
-  __device__ __forceinline__ void bind(double *d, int32_t *i) {
-    hd = d;
-    hi = i;
-  }
-
-  __device__ __forceinline__ void init(int k_, bool live) {
-    const int lane = threadIdx.x & 63;
-    k = k_;
-    const double d0 = live ? INFINITY : -INFINITY;
-    const int32_t i0 = live ? INT_MAX : INT_MIN;
-    for (int s = 0; s < k; ++s) {
-      hd[s * 64 + lane] = d0;
-      hi[s * 64 + lane] = i0;
-    }
-    root_d = d0;
-    root_i = i0;
-  }
-
-  __device__ __forceinline__ double kth() const { return root_d; }
-
-  // sift `dd, q` down from slot i within the first `size` slots
-  __device__ __forceinline__ void sift(int i, int size, double dd, int32_t q) {
-    const int lane = threadIdx.x & 63;
-    while (true) {
-      int c = 2 * i + 1;
-      if (c >= size) break;
-      double cd = hd[c * 64 + lane];
-      int32_t ci = hi[c * 64 + lane];
-      if (c + 1 < size) {
-        const double c2d = hd[(c + 1) * 64 + lane];
-        const int32_t c2i = hi[(c + 1) * 64 + lane];
-        if (cand_lt(cd, ci, c2d, c2i)) {
-          c = c + 1;
-          cd = c2d;
-          ci = c2i;
-        }
-      }
-      if (!cand_lt(dd, q, cd, ci)) break;  // the larger child does not exceed the item
-      hd[i * 64 + lane] = cd;
-      hi[i * 64 + lane] = ci;
-      i = c;
-    }
-    hd[i * 64 + lane] = dd;
-    hi[i * 64 + lane] = q;
-  }
-
-  template <bool = false>
-  __device__ __forceinline__ void offer(double dd, int32_t q) {
-    if (!(dd <= root_d)) return;
-    if (!cand_lt(dd, q, root_d, root_i)) return;
-    const int lane = threadIdx.x & 63;
-    sift(0, k, dd, q);
-    root_d = hd[lane];
-    root_i = hi[lane];
-  }
-
-  // heap sort: extract the worst into the last output slot, and so on
-  __device__ __forceinline__ void write(int k_, int32_t *out_ids, double *out_d2) {
-    const int lane = threadIdx.x & 63;
-    for (int size = k; size > 0; --size) {
-      const double d = hd[lane];
-      const int32_t i = hi[lane];
-      out_ids[size - 1] = i == INT_MAX ? -1 : i;
-      out_d2[size - 1] = d;
-      if (size > 1) sift(0, size - 1, hd[(size - 1) * 64 + lane], hi[(size - 1) * 64 + lane]);
-    }
-  }
-};
-
-// For external and root-based queries with k in (24, 50] the k best are
-// split: the lower M = K - R slots,
-// sorted, in LDS (slot-major like the heap above), the upper R slots in
-// registers with the segmented shift.  Entries mostly land near the k-th
-// slot, so most insertions stay in registers; one that reaches below them
-// shifts the LDS part of its own lane up by one.  The largest LDS entry is
-// mirrored in registers for the boundary test.  This keeps 2 or 3
-// wavefronts per SIMD where the whole set in LDS (the heap) allowed one, or
-// the whole set in registers two (k = 32).  (k = 51-100
-// keeps the heap: with R = 24, 40 or 48 the split set measured slower, the
-// larger R overflowing the register file.)
-template <int K, int R_>
-struct SplitSet {
-  static constexpr int R = R_;
-  static constexpr int M = K - R;
-  static constexpr int kSeg = 8;
-  double d[R];    // slots M .. K-1
-  int32_t id[R];
-  double md;      // slot M-1
-  int32_t mi;
-  double *ld;     // [M][64] this wavefront's lower slots
-  int32_t *li;
-
-  __device__ __forceinline__ void bind(double *d_, int32_t *i_) {
-    ld = d_;
-    li = i_;
-  }
-
-  // every register slot and slot M-1 lie above the K-k padding slots
-  // (K - k < M in every bucket that uses this set), so only the LDS part
-  // holds padding
-  __device__ __forceinline__ void init(int k, bool live) {
-    const int lane = threadIdx.x & 63;
-    for (int j = 0; j < M; ++j) {
-      const bool used = live && j >= K - k;
-      ld[j * 64 + lane] = used ? INFINITY : -INFINITY;
-      li[j * 64 + lane] = used ? INT_MAX : INT_MIN;
-    }
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      d[j] = live ? INFINITY : -INFINITY;
-      id[j] = live ? INT_MAX : INT_MIN;
-    }
-    md = live ? INFINITY : -INFINITY;
-    mi = live ? INT_MAX : INT_MIN;
-  }
-
-  __device__ __forceinline__ double kth() const { return d[R - 1]; }
-
-  template <int A, int B>
-  __device__ __forceinline__ void precedes(double dd, int32_t q, bool *lt) const {
-    bool tie = false;
-#pragma unroll
-    for (int j = A; j < B; ++j) {
-      lt[j - A] = dd < d[j];
-      tie = tie | (dd == d[j]);
-    }
-    if (__ballot(tie) != 0) {
-#pragma unroll
-      for (int j = A; j < B; ++j) lt[j - A] = lt[j - A] | ((dd == d[j]) & (q < id[j]));
-    }
-  }
-
-  // register slots [A, B), top segment first; below slot 0 is slot M-1
-  template <int B>
-  __device__ __forceinline__ void shift(double dd, int32_t q) {
-    constexpr int A = B > kSeg ? B - kSeg : 0;
-    bool lt[B - A];
-    precedes<A, B>(dd, q, lt);
-    const double cd = A > 0 ? d[A > 0 ? A - 1 : 0] : md;
-    const int32_t ci = A > 0 ? id[A > 0 ? A - 1 : 0] : mi;
-    const bool low = cand_lt(dd, q, cd, ci);
-#pragma unroll
-    for (int j = B - 1; j > A; --j) {
-      const double nd = lt[j - 1 - A] ? d[j - 1] : (lt[j - A] ? dd : d[j]);
-      const int32_t ni = lt[j - 1 - A] ? id[j - 1] : (lt[j - A] ? q : id[j]);
-      d[j] = nd;
-      id[j] = ni;
-    }
-    const double nd = low ? cd : (lt[0] ? dd : d[A]);
-    const int32_t ni = low ? ci : (lt[0] ? q : id[A]);
-    d[A] = nd;
-    id[A] = ni;
-    if (__ballot(low) != 0) {
-      if constexpr (A > 0)
-        this->template shift<A>(dd, q);
-      else if (low)
-        lds_insert(dd, q);
-    }
-  }
-
-  // the candidate precedes slot M-1, whose entry has moved to register
-  // slot 0: shift the larger LDS entries up and place it
-  __device__ __forceinline__ void lds_insert(double dd, int32_t q) {
-    const int lane = threadIdx.x & 63;
-    int j = M - 1;
-    for (; j > 0; --j) {
-      const double sd = ld[(j - 1) * 64 + lane];
-      const int32_t si = li[(j - 1) * 64 + lane];
-      if (!cand_lt(dd, q, sd, si)) break;
-      ld[j * 64 + lane] = sd;
-      li[j * 64 + lane] = si;
-    }
-    ld[j * 64 + lane] = dd;
-    li[j * 64 + lane] = q;
-    md = ld[(M - 1) * 64 + lane];
-    mi = li[(M - 1) * 64 + lane];
-  }
-
-  template <bool = false>
-  __device__ __forceinline__ void offer(double dd, int32_t q) {
-    if (!(dd <= d[R - 1])) return;
-    this->template shift<R>(dd, q);
-  }
-
-  __device__ __forceinline__ void write(int k, int32_t *out_ids, double *out_d2) const {
-    const int lane = threadIdx.x & 63;
-    int o = 0;
-    for (int j = K - k; j < M; ++j, ++o) {
-      const int32_t i = li[j * 64 + lane];
-      out_ids[o] = i == INT_MAX ? -1 : i;
-      out_d2[o] = ld[j * 64 + lane];
-    }
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      out_ids[o + j] = id[j] == INT_MAX ? -1 : id[j];
-      out_d2[o + j] = d[j];
-    }
   }
 };
 
@@ -604,42 +323,15 @@ constexpr int ext_team_size() {
   return K > 16 ? team_size<K>() : (K >= 8 ? 4 : 0);
 }
 
-// Per k bucket: the candidate set, its per-lane LDS slots, whether the
-// prescore runs in the shared order over a 64-entry stage (the LDS heap)
-// or each lane's near-first order over the whole window, and whether the
-// set is filled by a sorting network (the register sets; not k = 12, where
-// the fill adds two spilled dwords under the 96-VGPR cap and the query
-// measured 20% slower, while k = 8-24 otherwise gain 1-3%).
+// Per k bucket with one lane per query (k <= 16): the candidate set, and
+// whether the set is filled by a sorting network (not k = 12, where the
+// fill adds two spilled dwords under the 96-VGPR cap and the query
+// measured 20% slower, while k = 8-16 otherwise gain 1-3%).
 template <int K>
 struct HeapFor {
   using type = Heap<K>;
-  static constexpr int lds_slots = 0;
-  static constexpr bool shared_prescore = false;
   static constexpr bool sorted_fill = K != 12;
 };
-#define ZD_SPLIT_SET(KK, RR)                       \
-  template <>                                      \
-  struct HeapFor<KK> {                             \
-    using type = SplitSet<KK, RR>;                 \
-    static constexpr int lds_slots = KK - RR;      \
-    static constexpr bool shared_prescore = false; \
-    static constexpr bool sorted_fill = false;     \
-  };
-ZD_SPLIT_SET(32, 24)
-ZD_SPLIT_SET(40, 24)
-ZD_SPLIT_SET(50, 32)
-#undef ZD_SPLIT_SET
-template <int K>
-struct HeapFor_LdsHeap {
-  using type = LdsHeap<K>;
-  static constexpr int lds_slots = K;
-  static constexpr bool shared_prescore = true;
-  static constexpr bool sorted_fill = false;
-};
-template <>
-struct HeapFor<64> : HeapFor_LdsHeap<64> {};
-template <>
-struct HeapFor<100> : HeapFor_LdsHeap<100> {};
 
 // withinBox(C, p, -r) of Algorithm 3, squared: p in the box and every face
 // strictly farther than the k-th d2 (never true while N holds fewer than k,
@@ -660,9 +352,9 @@ __device__ __forceinline__ bool ball_inside(double px, double py, double pz, con
 __device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // sorted positions scored on either side of a query group before its walk
-// (all-points rows), per k bucket: 48 for the LDS-heap buckets (3% faster
-// than 32 at k = 64), 32 elsewhere (48, 64 and 96 measured no faster for
-// k = 32-50, 96 slower)
+// (all-points rows), per k bucket: 48 for k > 50, 32 elsewhere (in lane
+// teams 32, 48 and 64 measured within 1% of each other at k = 32, 50 and
+// 100)
 template <int K>
 constexpr int64_t prescore_reach() {
   return K >= 64 ? 48 : 32;
@@ -707,43 +399,8 @@ struct WaveSearch {
     return __ballot(w) != 0;
   }
 
-  // Every lane scores the sorted positions [a, b] (64 at a time through LDS)
-  // and the walk then skips them.  `own` is this lane's own sorted position,
-  // which enters as (+inf, INT_MAX) and so never precedes the k-th entry.
-  // (All-points groups only: an external query group covers many more tree
-  // points than its 64 queries and measured slower with a shared window;
-  // its lanes score their own leaves instead.  This shared order, one
-  // position at a time in LDS chunks of 64, serves the LDS-heap buckets,
-  // whose stage holds 64 entries; the register buckets use
-  // prescore_near_first.)
-  __device__ __forceinline__ void prescore(int64_t a, int64_t b, int64_t own) {
-    const int lane = threadIdx.x & 63;
-    for (int64_t c = a; c <= b; c += 64) {
-      const int64_t j = c + lane;
-      if (j <= b) {
-        Cand q;
-        q.x = t.X[j];
-        q.y = t.Y[j];
-        q.z = D == 3 ? t.Z[j] : 0.0;
-        q.id = t.id[j];
-        q.pad = 0;
-        stage[lane] = q;
-      }
-      __builtin_amdgcn_wave_barrier();
-      const int cnt = (int)min((int64_t)64, b - c + 1);
-      const int me = own >= c && own < c + 64 ? (int)(own - c) : -1;
-      for (int jj = 0; jj < cnt; ++jj) {
-        const Cand q = stage[jj];
-        const double dd = dist2<D>(px, py, pz, q.x, q.y, q.z);
-        h.offer(jj == me ? INFINITY : dd, jj == me ? INT_MAX : q.id);
-      }
-      __builtin_amdgcn_wave_barrier();
-    }
-    skip_lo = uni((int32_t)a);
-    skip_hi = uni((int32_t)b);
-  }
-
-  // The same positions, each lane in its own order: lane l (own position
+  // Every lane scores the sorted positions [a, b] around its group (the
+  // walk then skips them), each in its own order: lane l (own position
   // a + o) takes at step s the position a + ((o + m) mod cnt) for s odd and
   // a + ((o - m) mod cnt) for s even, m = (s + 1) / 2, so it meets its
   // Morton neighbours first and every other position of [a, b] exactly
@@ -1070,12 +727,11 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t h, uint32_t nb) {
 }
 
 // All-points rows: wavefront w answers sorted positions [64w, 64w + 64).
-// LDS per wavefront: the candidate stage (the whole prescore window for the
-// register candidate sets, 64 entries for the LDS heaps), plus the heap
+// LDS per wavefront: the candidate stage, which holds the whole prescore
+// window (the group and prescore_reach<K>() positions on either side).
 template <int K>
 constexpr size_t wave_lds_bytes() {
-  return (HeapFor<K>::shared_prescore ? 64 : 64 + 2 * prescore_reach<K>()) * sizeof(Cand) +
-         (size_t)HeapFor<K>::lds_slots * 64 * (sizeof(double) + sizeof(int32_t));
+  return (64 + 2 * prescore_reach<K>()) * sizeof(Cand);
 }
 
 // All-points rows in lane teams (TeamSet) for these buckets; their LDS is
@@ -1090,13 +746,12 @@ constexpr bool all_team() {
 }
 template <int K>
 constexpr size_t all_lds_bytes() {
-  return all_team<K>() ? (64 + 2 * prescore_reach<K>()) * sizeof(Cand) : wave_lds_bytes<K>();
+  return wave_lds_bytes<K>();
 }
 
 // Wavefronts per workgroup of a query launch: the requested 1, 2 or 4,
-// halved while the workgroup's LDS would exceed one CU's 160 KiB (only the
-// k > 32 buckets, whose candidate sets live wholly or partly in LDS, come
-// near it).
+// halved while the workgroup's LDS would exceed one CU's 160 KiB (a stage
+// of at most 160 candidates, 5 KB per wavefront, never comes near it).
 template <int K, bool kAll = false>
 int fit_waves(int want) {
   const size_t per = kAll ? all_lds_bytes<K>() : wave_lds_bytes<K>();
@@ -1109,11 +764,6 @@ template <int D, int K, bool E, bool P, bool TM>
 __device__ __forceinline__ void bind_lds(WaveSearch<D, K, E, P, TM> &s, char *smem, int w) {
   char *base = smem + (size_t)w * (TM ? all_lds_bytes<K>() : wave_lds_bytes<K>());
   s.stage = reinterpret_cast<Cand *>(base);
-  if constexpr (!TM && HeapFor<K>::lds_slots > 0) {
-    constexpr int kStage = HeapFor<K>::shared_prescore ? 64 : 64 + 2 * prescore_reach<K>();
-    double *hd = reinterpret_cast<double *>(base + kStage * sizeof(Cand));
-    s.h.bind(hd, reinterpret_cast<int32_t *>(hd + (size_t)HeapFor<K>::lds_slots * 64));
-  }
 }
 
 // Register budget of the all-points kernel.  At k = 10 it needs 85 VGPRs
@@ -1166,12 +816,8 @@ __device__ __forceinline__ void all_points_lanes(const TreeView &t, int k,
   // the group's own points and prescore_reach<K>() on either side (Morton neighbours
   // of every lane).  This tightens every lane's k-th distance before the
   // walk, which then skips these positions.
-  if constexpr (HeapFor<K>::shared_prescore)
-    s.prescore(max(c_lo, g0 - prescore_reach<K>()), min(c_hi, last + prescore_reach<K>()),
-               g0 + lane);
-  else
-    s.prescore_near_first(max(c_lo, g0 - prescore_reach<K>()),
-                          min(c_hi, last + prescore_reach<K>()), g0 + lane, k);
+  s.prescore_near_first(max(c_lo, g0 - prescore_reach<K>()),
+                        min(c_hi, last + prescore_reach<K>()), g0 + lane, k);
   // lowest common ancestor of the group's leaves
   const int32_t lf = uni(t.leaf_of[g0]), ll = uni(t.leaf_of[last]);
   int32_t G = ~lf;
@@ -1276,13 +922,12 @@ k_knn_all(TreeView t, int k, int32_t *__restrict__ out_ids,
 // External rows: wavefront w answers the Morton-sorted queries
 // order[64w .. 64w + 64); row r of the output belongs to query r.
 // Register budget of the external-query and root-based kernels: in lane
-// teams the all-points kernel's caps; with one lane per query: k = 16
-// capped at 128 VGPRs (4 wavefronts per SIMD instead of 3) and k = 24 and
-// 32 at 168 (3 instead of 2) measured 9-12% faster; k = 40 capped at 168 ran
-// 8% slower and keeps the compiler's choice, like the other buckets.
+// teams the all-points kernel's caps; with one lane per query, k = 16
+// capped at 128 VGPRs (4 wavefronts per SIMD instead of 3) measured 9-12%
+// faster, and the other buckets keep the compiler's choice.
 template <int K>
 constexpr int knn_root_min_waves() {
-  return K == 16 ? 4 : (K == 24 || K == 32 ? 3 : 1);
+  return K == 16 ? 4 : 1;
 }
 template <int K, bool kTeam>
 constexpr int knn_ext_min_waves() {
