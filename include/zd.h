@@ -283,11 +283,11 @@ ZD_API zd_status zd_knn_backward_det(int32_t dim, const double *xyz, int64_t str
  * points are the tree's current ones (xyz by id, as given to zd_build and
  * the inserts); ids/grad_d2: (device) [cap][k], the rows of zd_knn(t,
  * NULL, cap, k, ...) on this tree, unchanged since; grad_xyz: (device)
- * [dim][cap], overwritten (zero for dead ids).  Results equal
- * zd_knn_backward's up to the order of the floating-point additions.
- * Read-only on the tree (may run beside queries, as zd_knn).  Errors:
- * ZD_EINVAL (also while in-place small batches are pending: use
- * zd_knn_backward then), ZD_EKMAX, ZD_EDEVICE. */
+ * [dim][cap], overwritten (zero for dead ids).  Points that small inserts
+ * placed in place (pending batches) take their rows in a second pass, in
+ * the order of their side pool.  Results equal zd_knn_backward's up to the
+ * order of the floating-point additions.  Read-only on the tree (may run
+ * beside queries, as zd_knn).  Errors: ZD_EINVAL, ZD_EKMAX, ZD_EDEVICE. */
 ZD_API zd_status zd_knn_backward_tree(zd_tree tree, int32_t k, const int32_t *ids,
                                       const double *grad_d2, double *grad_xyz, void *stream);
 

@@ -8,9 +8,8 @@ library's scatter-add kernel,
     dL/dp += 2 (p - q) g,   dL/dq -= 2 (p - q) g,
 for every row p, neighbour q and upstream gradient g: in the tree's Morton
 order (zd_knn_backward_tree) when the tree is unchanged since the forward
-pass and holds no in-place batches, else over the rows in id order
-(zd_knn_backward), or without atomics in a fixed order when
-deterministic=True (zd_knn_backward_det).  Selection itself is not
+pass, else over the rows in id order (zd_knn_backward), or without atomics
+in a fixed order when deterministic=True (zd_knn_backward_det).  Selection itself is not
 differentiated, as usual for nearest-neighbour losses.
 """
 from __future__ import annotations
@@ -38,7 +37,7 @@ class ZdKnnSqDist(torch.autograd.Function):
             else grad_d2.contiguous()
         tree = ctx.tree
         if (not ctx.deterministic and tree.handle is not None and tree.version == ctx.version
-                and tree.cap == xyz.shape[1] and tree.pending() == (0, 0)):
+                and tree.cap == xyz.shape[1]):
             grad = tree.knn_backward(ids, g)
         else:
             grad = zd_knn_backward(xyz.detach(), ids, g, deterministic=ctx.deterministic)

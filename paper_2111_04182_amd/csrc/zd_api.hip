@@ -634,12 +634,14 @@ zd_status zd_knn_backward_tree(zd_tree t, int32_t k, const int32_t *ids,
   if (!t || k < 1) return ZD_EINVAL;
   if (k > ZD_KMAX) return ZD_EKMAX;
   if (t->broken) return ZD_EDEVICE;
-  if (t->pend.any()) return ZD_EINVAL;  // in-place batches pending: zd_knn_backward applies
   if (t->cap > 0 && (!ids || !grad_d2 || !grad_xyz)) return ZD_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = join_query_stream(t, s, false);
+  // (the side pool's entries, while small inserts are pending in place)
+  const int64_t pcap = t->pend.n_pool > 0 ? t->pend.pcap : 0;
   if (e == hipSuccess && t->cap > 0)
-    e = knn_backward_tree(t->dim, t->view(), t->slot_of, t->cap, k, ids, grad_d2, grad_xyz, s);
+    e = knn_backward_tree(t->dim, t->view(), t->slot_of, t->cap, pcap, k, ids, grad_d2, grad_xyz,
+                          s);
   if (e == hipSuccess) e = join_query_stream(t, s, true);
   return to_status(e);
 }

@@ -172,95 +172,135 @@ namespace zd {
 // atomics into a buffer in sorted order (near the row's own position, not
 // at a random id).  The tile's sums are stored to a second sorted-order
 // buffer, and a last pass writes the sum of the two at each position's id.
+// Points that small inserts placed in the side pool (pending in-place
+// batches) have their rows taken by a second kernel, one thread per pool
+// entry, and their terms summed in a pool-order buffer; a deleted point's
+// row is empty (its slot's coordinate is NaN, its row all -1).
 // ---------------------------------------------------------------------------
 constexpr int kBwdTile = 1024;
 constexpr int kBwdBatch = 8;  // neighbours whose loads a thread issues together
 static_assert(kBwdBatch == 8, "the vector row loads below take eight entries");
 
+// The terms of row r (point p): each neighbour's share is added to the LDS
+// tile sums (a sorted position inside [t0, t0 + kBwdTile), kTile only), to
+// gs (another sorted position) or to gp (a pool entry); the row's own terms
+// are summed in own.
+template <int D, bool kVec, bool kTile>
+__device__ __forceinline__ void bwd_row(const TreeView &t, const int32_t *__restrict__ slot_of,
+                                        int64_t cap, int k, const int32_t *__restrict__ ids,
+                                        const double *__restrict__ g, int64_t r, const double *p,
+                                        double *own, int64_t t0, double *acc, double *gs,
+                                        double *gp, int64_t pcap) {
+  // kBwdBatch neighbours at a time, each step's loads issued together (the
+  // row, then the positions, then their coordinates): every load reads a
+  // clamped, valid address and the invalid ones are dropped after it, so no
+  // branch splits the batch
+  const int32_t nmax = (int32_t)t.n - 1;
+  for (int j0 = 0; j0 < k; j0 += kBwdBatch) {
+    int32_t q[kBwdBatch], sq[kBwdBatch];
+    double w[kBwdBatch];
+    if constexpr (kVec) {
+      // k a multiple of 4 and both tables 16-byte aligned: the row's eight
+      // entries in two int4 and four double2 loads (a short row reads its
+      // first four twice and drops the copy)
+      const bool hi = j0 + 4 < k;
+      const int64_t e0 = r * k + j0, e1 = hi ? e0 + 4 : e0;
+      const int4 a = *reinterpret_cast<const int4 *>(ids + e0);
+      const int4 b = *reinterpret_cast<const int4 *>(ids + e1);
+      const double2 w0 = *reinterpret_cast<const double2 *>(g + e0);
+      const double2 w1 = *reinterpret_cast<const double2 *>(g + e0 + 2);
+      const double2 w2 = *reinterpret_cast<const double2 *>(g + e1);
+      const double2 w3 = *reinterpret_cast<const double2 *>(g + e1 + 2);
+      q[0] = a.x, q[1] = a.y, q[2] = a.z, q[3] = a.w;
+      q[4] = hi ? b.x : -1, q[5] = hi ? b.y : -1, q[6] = hi ? b.z : -1, q[7] = hi ? b.w : -1;
+      w[0] = w0.x, w[1] = w0.y, w[2] = w1.x, w[3] = w1.y;
+      w[4] = w2.x, w[5] = w2.y, w[6] = w3.x, w[7] = w3.y;
+    } else {
+#pragma unroll
+      for (int u = 0; u < kBwdBatch; ++u) {
+        const int64_t e = r * k + min(j0 + u, k - 1);
+        q[u] = j0 + u < k ? ids[e] : -1;
+        w[u] = g[e];
+      }
+    }
+    // sq: a sorted position (>= 0), a pool entry e as -2 - e, or -1 for
+    // padding and dead ids
+#pragma unroll
+    for (int u = 0; u < kBwdBatch; ++u) {
+      const bool in = q[u] >= 0 && q[u] < cap;
+      const int32_t v = slot_of[in ? q[u] : 0];
+      const bool pool = in && v >= kPoolSlot && (int64_t)(v - kPoolSlot) < pcap;
+      sq[u] = in && v >= 0 && v <= nmax ? v : (pool ? -2 - (v - kPoolSlot) : -1);
+    }
+    double pq[kBwdBatch][3];
+#pragma unroll
+    for (int u = 0; u < kBwdBatch; ++u) {
+      const bool pool = sq[u] <= -2;
+      const int32_t v = pool ? -2 - sq[u] : (sq[u] < 0 ? 0 : sq[u]);
+      pq[u][0] = (pool ? t.pX : t.X)[v];
+      pq[u][1] = (pool ? t.pY : t.Y)[v];
+      pq[u][2] = D == 3 ? (pool ? t.pZ : t.Z)[v] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kBwdBatch; ++u) {
+      if (sq[u] == -1) continue;
+      const int64_t ls = sq[u] - t0;
+      const bool local = kTile && sq[u] >= 0 && ls >= 0 && ls < kBwdTile;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double term = 2.0 * (p[c] - pq[u][c]) * w[u];
+        own[c] += term;
+        if (local) atomicAdd(&acc[c * kBwdTile + ls], -term);
+        else if (sq[u] >= 0) unsafeAtomicAdd(&gs[c * t.n + sq[u]], -term);
+        else unsafeAtomicAdd(&gp[c * pcap + (-2 - sq[u])], -term);
+      }
+    }
+  }
+}
+
 template <int D, bool kVec>
 __global__ void __launch_bounds__(kBwdTile)
     k_knn_backward_tree(TreeView t, const int32_t *__restrict__ slot_of, int64_t cap, int k,
                         const int32_t *__restrict__ ids, const double *__restrict__ g,
-                        double *gs, double *__restrict__ gt) {
-  __shared__ double acc[D][kBwdTile];
+                        double *gs, double *__restrict__ gt, double *gp, int64_t pcap) {
+  __shared__ double acc[D * kBwdTile];
   const int tid = threadIdx.x;
   const int64_t t0 = (int64_t)blockIdx.x * kBwdTile;
   const int64_t i = t0 + tid;
 #pragma unroll
-  for (int c = 0; c < D; ++c) acc[c][tid] = 0.0;
+  for (int c = 0; c < D; ++c) acc[c * kBwdTile + tid] = 0.0;
   __syncthreads();
   if (i < t.n) {
     const int64_t r = t.id[i];
     const double p[3] = {t.X[i], t.Y[i], D == 3 ? t.Z[i] : 0.0};
     double own[3] = {0.0, 0.0, 0.0};
-    // kBwdBatch neighbours at a time, each step's loads issued together (the
-    // row, then the positions, then their coordinates): every load reads a
-    // clamped, valid address and the invalid ones are dropped after it, so
-    // no branch splits the batch
-    const int32_t nmax = (int32_t)t.n - 1;
-    for (int j0 = 0; j0 < k; j0 += kBwdBatch) {
-      int32_t q[kBwdBatch], sq[kBwdBatch];
-      double w[kBwdBatch];
-      if constexpr (kVec) {
-        // k a multiple of 4 and both tables 16-byte aligned: the row's
-        // eight entries in two int4 and four double2 loads (a short row
-        // reads its first four twice and drops the copy)
-        const bool hi = j0 + 4 < k;
-        const int64_t e0 = r * k + j0, e1 = hi ? e0 + 4 : e0;
-        const int4 a = *reinterpret_cast<const int4 *>(ids + e0);
-        const int4 b = *reinterpret_cast<const int4 *>(ids + e1);
-        const double2 w0 = *reinterpret_cast<const double2 *>(g + e0);
-        const double2 w1 = *reinterpret_cast<const double2 *>(g + e0 + 2);
-        const double2 w2 = *reinterpret_cast<const double2 *>(g + e1);
-        const double2 w3 = *reinterpret_cast<const double2 *>(g + e1 + 2);
-        q[0] = a.x, q[1] = a.y, q[2] = a.z, q[3] = a.w;
-        q[4] = hi ? b.x : -1, q[5] = hi ? b.y : -1, q[6] = hi ? b.z : -1, q[7] = hi ? b.w : -1;
-        w[0] = w0.x, w[1] = w0.y, w[2] = w1.x, w[3] = w1.y;
-        w[4] = w2.x, w[5] = w2.y, w[6] = w3.x, w[7] = w3.y;
-      } else {
+    bwd_row<D, kVec, true>(t, slot_of, cap, k, ids, g, r, p, own, t0, acc, gs, gp, pcap);
 #pragma unroll
-        for (int u = 0; u < kBwdBatch; ++u) {
-          const int64_t e = r * k + min(j0 + u, k - 1);
-          q[u] = j0 + u < k ? ids[e] : -1;
-          w[u] = g[e];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kBwdBatch; ++u) {
-        const bool in = q[u] >= 0 && q[u] < cap;
-        const int32_t v = slot_of[in ? q[u] : 0];
-        sq[u] = in && v >= 0 && v <= nmax ? v : -1;  // -1: padding or a dead id
-      }
-      double pq[kBwdBatch][3];
-#pragma unroll
-      for (int u = 0; u < kBwdBatch; ++u) {
-        const int32_t v = sq[u] < 0 ? 0 : sq[u];
-        pq[u][0] = t.X[v];
-        pq[u][1] = t.Y[v];
-        pq[u][2] = D == 3 ? t.Z[v] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < kBwdBatch; ++u) {
-        if (sq[u] < 0) continue;
-        const int64_t ls = sq[u] - t0;
-        const bool local = ls >= 0 && ls < kBwdTile;
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-          const double term = 2.0 * (p[c] - pq[u][c]) * w[u];
-          own[c] += term;
-          if (local) atomicAdd(&acc[c][ls], -term);
-          else unsafeAtomicAdd(&gs[c * t.n + sq[u]], -term);
-        }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < D; ++c) atomicAdd(&acc[c][tid], own[c]);
+    for (int c = 0; c < D; ++c) atomicAdd(&acc[c * kBwdTile + tid], own[c]);
   }
   __syncthreads();
   if (i < t.n) {
 #pragma unroll
-    for (int c = 0; c < D; ++c) gt[c * t.n + i] = acc[c][tid];
+    for (int c = 0; c < D; ++c) gt[c * t.n + i] = acc[c * kBwdTile + tid];
   }
+}
+
+// rows of the live pool entries (a NaN coordinate marks an unused or
+// deleted entry)
+template <int D, bool kVec>
+__global__ void k_knn_backward_pool(TreeView t, const int32_t *__restrict__ slot_of, int64_t cap,
+                                    int k, const int32_t *__restrict__ ids,
+                                    const double *__restrict__ g, double *gs, double *gp,
+                                    int64_t pcap) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= pcap) return;
+  const double p[3] = {t.pX[e], t.pY[e], D == 3 ? t.pZ[e] : 0.0};
+  if (isnan(p[0])) return;
+  const int64_t r = t.pid[e];
+  double own[3] = {0.0, 0.0, 0.0};
+  bwd_row<D, kVec, false>(t, slot_of, cap, k, ids, g, r, p, own, 0, nullptr, gs, gp, pcap);
+#pragma unroll
+  for (int c = 0; c < D; ++c) unsafeAtomicAdd(&gp[c * pcap + e], own[c]);
 }
 
 template <int D>
@@ -274,36 +314,54 @@ __global__ void k_unsort_grad(const int32_t *__restrict__ id, int64_t n,
   for (int c = 0; c < D; ++c) grad[c * stride + r] = gt[c * n + i] + gs[c * n + i];
 }
 
+template <int D>
+__global__ void k_unsort_pool(TreeView t, int64_t pcap, const double *__restrict__ gp,
+                              int64_t stride, double *grad) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= pcap || isnan(t.pX[e])) return;
+  const int64_t r = t.pid[e];
+#pragma unroll
+  for (int c = 0; c < D; ++c) grad[c * stride + r] = gp[c * pcap + e];
+}
+
+template <int D, bool kVec>
+void launch_backward_tree(const TreeView &t, const int32_t *slot_of, int64_t cap, int k,
+                          const int32_t *ids, const double *g, double *gs, double *gt, double *gp,
+                          int64_t pcap, double *grad, hipStream_t s) {
+  const unsigned tiles = (unsigned)((t.n + kBwdTile - 1) / kBwdTile);
+  const unsigned grid = (unsigned)((t.n + 255) / 256);
+  k_knn_backward_tree<D, kVec><<<tiles, kBwdTile, 0, s>>>(t, slot_of, cap, k, ids, g, gs, gt, gp,
+                                                          pcap);
+  if (pcap > 0) {
+    const unsigned pgrid = (unsigned)((pcap + 255) / 256);
+    k_knn_backward_pool<D, kVec><<<pgrid, 256, 0, s>>>(t, slot_of, cap, k, ids, g, gs, gp, pcap);
+    k_unsort_pool<D><<<pgrid, 256, 0, s>>>(t, pcap, gp, cap, grad);
+  }
+  k_unsort_grad<D><<<grid, 256, 0, s>>>(t.id, t.n, gs, gt, cap, grad);
+}
+
 hipError_t knn_backward_tree(int dim, const TreeView &t, const int32_t *slot_of, int64_t cap,
-                             int k, const int32_t *ids, const double *g, double *grad,
-                             hipStream_t s) {
-  // every live id is written by the last pass; only dead ids need the zero
-  hipError_t e = t.n < cap ? fill_f64(grad, 0.0, (int64_t)dim * cap, s) : hipSuccess;
+                             int64_t pcap, int k, const int32_t *ids, const double *g,
+                             double *grad, hipStream_t s) {
+  // every id of the sorted arrays and of the live pool entries is written by
+  // the last passes; only dead or unplaced ids need the zero
+  hipError_t e = t.n + pcap < cap || pcap > 0 ? fill_f64(grad, 0.0, (int64_t)dim * cap, s)
+                                              : hipSuccess;
   if (e != hipSuccess || t.n <= 0) return e;
+  const int64_t ns = (int64_t)dim * t.n, np = (int64_t)dim * pcap;
   double *gs = nullptr;
-  e = dev_alloc_n(&gs, 2 * (int64_t)dim * t.n, s);
-  if (e == hipSuccess) e = fill_f64(gs, 0.0, (int64_t)dim * t.n, s);
+  e = dev_alloc_n(&gs, 2 * ns + np, s);
+  if (e == hipSuccess) e = fill_f64(gs, 0.0, ns, s);
+  if (e == hipSuccess && np > 0) e = fill_f64(gs + 2 * ns, 0.0, np, s);
   if (e == hipSuccess) {
-    double *gt = gs + (int64_t)dim * t.n;
-    const unsigned tiles = (unsigned)((t.n + kBwdTile - 1) / kBwdTile);
-    const unsigned grid = (unsigned)((t.n + 255) / 256);
+    double *gt = gs + ns, *gp = pcap > 0 ? gs + 2 * ns : nullptr;
     const bool vec = k % 4 == 0 && (uintptr_t)ids % 16 == 0 && (uintptr_t)g % 16 == 0;
     if (dim == 3) {
-      if (vec)
-        k_knn_backward_tree<3, true>
-            <<<tiles, kBwdTile, 0, s>>>(t, slot_of, cap, k, ids, g, gs, gt);
-      else
-        k_knn_backward_tree<3, false>
-            <<<tiles, kBwdTile, 0, s>>>(t, slot_of, cap, k, ids, g, gs, gt);
-      k_unsort_grad<3><<<grid, 256, 0, s>>>(t.id, t.n, gs, gt, cap, grad);
+      if (vec) launch_backward_tree<3, true>(t, slot_of, cap, k, ids, g, gs, gt, gp, pcap, grad, s);
+      else launch_backward_tree<3, false>(t, slot_of, cap, k, ids, g, gs, gt, gp, pcap, grad, s);
     } else {
-      if (vec)
-        k_knn_backward_tree<2, true>
-            <<<tiles, kBwdTile, 0, s>>>(t, slot_of, cap, k, ids, g, gs, gt);
-      else
-        k_knn_backward_tree<2, false>
-            <<<tiles, kBwdTile, 0, s>>>(t, slot_of, cap, k, ids, g, gs, gt);
-      k_unsort_grad<2><<<grid, 256, 0, s>>>(t.id, t.n, gs, gt, cap, grad);
+      if (vec) launch_backward_tree<2, true>(t, slot_of, cap, k, ids, g, gs, gt, gp, pcap, grad, s);
+      else launch_backward_tree<2, false>(t, slot_of, cap, k, ids, g, gs, gt, gp, pcap, grad, s);
     }
     e = hipGetLastError();
   }

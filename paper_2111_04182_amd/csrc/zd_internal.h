@@ -416,8 +416,8 @@ hipError_t knn_backward_det(int dim, const double *xyz, int64_t stride, int64_t 
 // Backward of a tree's own all-points rows (rows by id, cap of them), in
 // the tree's Morton order with in-tile sums in LDS (zd_grad.hip).
 hipError_t knn_backward_tree(int dim, const TreeView &t, const int32_t *slot_of, int64_t cap,
-                             int k, const int32_t *ids, const double *g, double *grad,
-                             hipStream_t s);
+                             int64_t pcap, int k, const int32_t *ids, const double *g,
+                             double *grad, hipStream_t s);
 hipError_t count_outside_box(int dim, const double *xyz, int64_t m, const double *lo,
                              const double *hi, int32_t *counter, hipStream_t s);
 hipError_t box_reduce(int dim, const double *xyz, int64_t n, double *out_lo_hi, hipStream_t s);

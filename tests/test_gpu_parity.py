@@ -310,7 +310,7 @@ def test_backward_in_tree_order(dim, dead):
     1,024-point tiles: k = 8 and 12 (vector row loads; 12 with a half batch),
     k = 13 (one scalar batch and a ragged one), rows read through an
     unaligned view (scalar loads), with every id live or with dead rows
-    after a streaming delete."""
+    after a streaming delete, then with small batches pending in place."""
     n = 5000 if dim == 3 else 4000
     P = W.uniform(n, dim, 412 + dim)
     box = (np.zeros(dim), np.ones(dim))
@@ -336,11 +336,26 @@ def test_backward_in_tree_order(dim, dead):
         assert np.abs(got - plain).max() <= tol
         if dead:
             assert np.all(got[np.arange(0, n, 7)] == 0.0)
-    # in-place batches pending: the tree path refuses, autograd falls back
-    g.insert(dev(W.uniform(3, dim, 415) * 0.5 + 0.25))
-    assert g.pending()[0] > 0
-    with pytest.raises(zd.ZdError):
-        g.knn_backward(*g.knn(8))
+    # in-place batches pending: points in the side pool (their rows in the
+    # pool pass) and dead slots
+    P2 = W.uniform(3, dim, 415) * 0.5 + 0.25
+    g.insert(dev(P2))
+    g.delete(torch.tensor([1, 2, 3], dtype=torch.int32, device="cuda"))
+    assert g.pending()[0] > 0 and g.pending()[1] > 0
+    allp = np.concatenate([P, P2])
+    for k in (8, 13):
+        ids, d2 = g.knn(k)
+        idn = ids.cpu().numpy()
+        assert np.all(idn[[1, 2, 3]] == -1)
+        wn = np.where(idn >= 0, rng.uniform(0.5, 2, idn.shape), 0.0)
+        ref = oracle.knn_grad(allp, idn, wn)
+        tol = 1e-13 * max(np.abs(ref).max(), 1.0)
+        w = torch.from_numpy(wn).cuda()
+        got = g.knn_backward(ids, w).cpu().numpy().T
+        assert np.abs(got - ref).max() <= tol, ("pending", k)
+        assert np.all(got[[1, 2, 3]] == 0.0)
+        plain = zd.zd_knn_backward(dev(allp), ids, w).cpu().numpy().T
+        assert np.abs(got - plain).max() <= tol
     g.close()
 
 
@@ -354,7 +369,8 @@ def test_autograd_function(deterministic):
     loss.backward()
     ref = oracle.knn_grad(P, ids.cpu().numpy(), np.ones((2000, 6)))
     assert np.allclose(xyz.grad.cpu().numpy().T, ref, rtol=1e-12, atol=1e-13)
-    # with an in-place batch pending the backward takes the id-order kernel
+    # with an in-place batch pending (the tree kernel takes the side pool's rows
+    # in its second pass)
     Q = W.uniform(5, 3, 411) * 0.5 + 0.25
     g.insert(dev(Q))
     P2 = np.concatenate([P, Q])
