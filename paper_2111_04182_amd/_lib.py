@@ -264,8 +264,9 @@ def zd_knn_backward(xyz: torch.Tensor, ids: torch.Tensor, grad_d2: torch.Tensor,
 def zd_knn_backward_tree(tree, dim: int, cap: int, ids: torch.Tensor, grad_d2: torch.Tensor,
                          grad_xyz: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """zd_knn_backward for the tree's own all-points rows ids [cap, k], in the
-    tree's Morton order (tree: a zd_tree handle with no pending in-place
-    batches).  Returns the gradient as SoA (dim, cap)."""
+    tree's Morton order (tree: a zd_tree handle, unchanged since the rows
+    were computed; points pending in place take a second pass).  Returns
+    the gradient as SoA (dim, cap)."""
     rows, k = ids.shape
     if rows != cap:
         raise ValueError("ids must hold one row per id of the tree")
